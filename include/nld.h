@@ -1,0 +1,159 @@
+/* nld.h — C ABI of libnld: NFFT-accelerated nonlocal image denoising on MI355X (gfx950).
+ *
+ * Method: arXiv 2407.06834, "Efficient nonlocal linear image denoising: bilevel
+ * optimization with Nonequispaced Fast Fourier Transform and matrix-free preconditioning".
+ *
+ * The library solves the nonlocal system of the paper's Sec. 2.6 (discretised state
+ * equation), written with alpha = mu / lambda as
+ *
+ *     (I + alpha L) u = f,      L = diag(D) - W,   D = W 1,
+ *
+ * where W = sum_l w_l K_l is the extended Gaussian ANOVA kernel of Sec. 2.5/2.6 over
+ * per-pixel features split into windows of at most three dimensions,
+ *     K_l(i, j) = exp(-||F_i[W_l] - F_j[W_l]||^2 / sigma_l^2),
+ * each K_l v evaluated by the NFFT fast Gauss summation of Sec. 3 (spreading, FFT,
+ * multiplication by the kernel's Fourier coefficients, inverse FFT, gathering), inside the
+ * deflated Jacobi-preconditioned CG of Sec. 4.3 / 5.4.
+ *
+ * Conventions for every entry point
+ *   - Vector and feature pointers are DEVICE pointers to contiguous arrays allocated and
+ *     owned by the caller (e.g. torch tensors' data_ptr()).  Their element type is the
+ *     plan's precision: float for NLD_FP32, double for NLD_FP64.  D is always double.
+ *   - Work is enqueued on the caller's stream `s` (0 = the null stream).
+ *   - Arguments are validated on the host before any launch; on NLD_E_INVAL nothing is
+ *     written.  nld_last_error() returns a thread-local message for the last failure.
+ *   - One plan is used from one stream at a time; plans are not thread-safe.
+ *   - Results are deterministic: the same inputs give bitwise-identical outputs.
+ */
+#ifndef NLD_H
+#define NLD_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nld_plan_s* nfft_plan_t;
+
+typedef enum {
+  NLD_OK = 0,
+  NLD_E_INVAL = 1,     /* invalid argument; nothing launched, outputs untouched        */
+  NLD_E_NOMEM = 2,     /* device allocation failed                                      */
+  NLD_E_HIP = 3,       /* a HIP runtime call failed (message names it)                  */
+  NLD_E_NOCONV = 4,    /* CG hit maxit; u holds the last iterate, info is filled        */
+  NLD_E_BREAKDOWN = 5, /* non-finite or non-positive CG scalar; u holds the last iterate */
+  NLD_E_STATE = 6      /* request incompatible with the plan's state                    */
+} nld_status;
+
+typedef enum { NLD_FP32 = 0, NLD_FP64 = 1 } nld_prec;
+
+/* Kernel descriptor (host memory, copied at plan time).
+ *   n_windows   L >= 1 windows; win_dim[l] in {1,2,3}; win_feat lists the feature rows of
+ *               each window back to back (sum of win_dim entries, each in [0, d)).
+ *   sigma       [L], > 0: Gaussian width of window l (kernel exp(-r^2 / sigma^2), Sec. 2.6).
+ *   weight      [L], >= 0: window weight w_l (the paper uses 1/L).
+ *   bandwidth   M, the number of Fourier coefficients per dimension (even, 8..256), used for
+ *               every window; 0 selects M per window from sigma_l, the data range and
+ *               matvec_tol.  win_bandwidth (optional, may be NULL) overrides per window.
+ *   cutoff      m, window half-width in grid cells (1..8); 0 selects it from matvec_tol.
+ *   oversampling  sigma_os >= 1.25; the grid has n = next power of two >= sigma_os * M
+ *               points per dimension (n <= 256).
+ *   matvec_tol  target relative error of K_l v when M or m are selected automatically.
+ *   prec        arithmetic of features, grids and vectors.  CG inner products, the
+ *               deflation means, D and the Laplacian epilogue are FP64 in both modes.
+ */
+typedef struct {
+  int32_t n_windows;
+  const int32_t* win_dim;
+  const int32_t* win_feat;
+  const double* sigma;
+  const double* weight;
+  int32_t bandwidth;
+  const int32_t* win_bandwidth;
+  int32_t cutoff;
+  double oversampling;
+  double matvec_tol;
+  nld_prec prec;
+} nld_kernel_desc;
+
+/* Per-window parameters chosen by the plan (for reports and tests). */
+typedef struct {
+  int32_t dims_kept;       /* window dimensions with a nonzero data range               */
+  int32_t bandwidth;       /* M                                                          */
+  int32_t grid;            /* n                                                          */
+  int32_t cutoff;          /* m                                                          */
+  double compression[3];   /* torus compression a per kept dimension                    */
+  double lo[3], hi[3];     /* data range per kept dimension                             */
+} nld_window_info;
+
+/* Build a plan over N nodes with d features stored SoA ([d][N], element type of prec):
+ * per-window torus scaling (data range reduction), Fourier multipliers, tile keys and the
+ * stable counting sort of the nodes by grid tile.  Blocks until the plan is ready.
+ * Paper Sec. 3 (fast Gauss summation) and Sec. 5 (windows of at most three features). */
+nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t d,
+                     const nld_kernel_desc* desc, hipStream_t s);
+
+/* Release every device buffer of the plan (enqueued on the plan's last stream). */
+nld_status nfft_plan_destroy(nfft_plan_t plan);
+
+/* Copy the chosen parameters of window l into *info (host). */
+nld_status nfft_plan_window_info(nfft_plan_t plan, int32_t l, nld_window_info* info);
+
+/* Number of nodes N and windows L of the plan. */
+nld_status nfft_plan_size(nfft_plan_t plan, int64_t* N, int32_t* L, nld_prec* prec);
+
+/* D = W~ 1 (FP64, device [N]): the degree vector of the approximated kernel, self term
+ * included (Sec. 2.6: eta = D - sum_l w_l is the zero-diagonal degree). */
+nld_status degree_vector(nfft_plan_t plan, double* D, hipStream_t s);
+
+/* y = W~ v = sum_l w_l K~_l v (self term included).  Asynchronous.  Sec. 3. */
+nld_status anova_matvec(nfft_plan_t plan, const void* v, void* y, hipStream_t s);
+
+/* y = L~ v = D o v - W~ v with the plan's own D, evaluated in FP64 before the final
+ * rounding to the plan's precision (L~ 1 = 0 exactly).  Asynchronous.  Sec. 2.6. */
+nld_status laplacian_matvec(nfft_plan_t plan, const void* v, void* y, hipStream_t s);
+
+typedef struct {
+  double tol;        /* stop when ||r_k||_2 <= tol * ||f - mean(f)||_2 (recursive residual) */
+  int32_t maxit;     /* maximum number of iterations (operator applications)              */
+  int32_t use_u0;    /* 1: u holds the initial guess on entry; 0: start from f (Sec. 5.3)  */
+  int32_t precond;   /* 1: Jacobi preconditioner P = I + alpha diag(eta); 0: none          */
+  int32_t deflate;   /* 1: change of basis removing the eigenvector 1 (Sec. 4.2, 5.4)      */
+  int32_t true_residual; /* 1: also compute the true residual at exit (one more matvec)     */
+  int32_t timing;    /* 1: time every operator application with HIP events on the stream s   */
+} nld_pcg_opts;
+
+typedef struct {
+  int32_t iters;        /* CG iterations (operator applications after the initial residual) */
+  double relres_rec;    /* recursive residual / ||f_perp||                                   */
+  double relres_true;   /* true residual / ||f_perp|| (if requested, else -1)                */
+  double kappa_est;     /* 2 alpha max(eta) + 1 (paper Sec. 5.3 condition estimate)          */
+  double ms_solve;      /* wall time of the solve, ms                                        */
+  double ms_matvec;     /* mean duration of one operator application (if timing), ms         */
+  int32_t matvecs_timed;/* operator applications that entered the mean                       */
+  nld_status status;
+} nld_pcg_info;
+
+/* Solve (I + alpha L~) u = f with deflated Jacobi PCG (Sec. 4.3.2, 5.4), projector form:
+ * mean(f) is kept exactly and CG runs on the complement of the constant vector with the
+ * preconditioner s = Pi (r / P), P = 1 + alpha eta, Pi = I - 1 1^T / N.  A constant f is
+ * returned unchanged with 0 iterations.  Blocks until done; fills *info (host). */
+nld_status pcg_solve(nfft_plan_t plan, double alpha, const void* f, void* u,
+                     const nld_pcg_opts* opts, nld_pcg_info* info, hipStream_t s);
+
+/* Features of an n1 x n2 image (device, row-major, element type of prec) into the SoA
+ * matrix features [d][N] (device), d = 2*with_pos + (2 rho + 1)^2, N = n1 n2: position
+ * (col/n2, row/n1) then the patch intensities of radius rho in raster order of the offsets,
+ * zero outside the image (paper Sec. 5, patches).  Asynchronous. */
+nld_status features_from_image(const void* img, int32_t n1, int32_t n2, int32_t rho,
+                               int32_t with_pos, nld_prec prec, void* features, hipStream_t s);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char* nld_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLD_H */

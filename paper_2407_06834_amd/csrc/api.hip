@@ -1,0 +1,230 @@
+// extern "C" entry points of libnld: argument validation, error reporting, dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+
+#include "nld_internal.h"
+
+struct nld_plan_s {
+  nld::Plan P;
+};
+
+namespace nld {
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace nld
+
+namespace {
+
+nld_status fail(nld_status st, const std::string& msg) {
+  nld::set_error(msg);
+  return st;
+}
+
+template <typename F>
+nld_status guarded(const char* name, F&& body) {
+  try {
+    return body();
+  } catch (const nld::HipError& e) {
+    return fail(NLD_E_HIP, std::string(name) + ": " + e.where + ": " + hipGetErrorString(e.err));
+  } catch (const std::bad_alloc&) {
+    return fail(NLD_E_NOMEM, std::string(name) + ": host allocation failed");
+  } catch (const std::invalid_argument& e) {
+    return fail(NLD_E_INVAL, std::string(name) + ": " + e.what());
+  } catch (const std::exception& e) {
+    return fail(NLD_E_STATE, std::string(name) + ": " + e.what());
+  }
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* nld_last_error(void) { return nld::g_last_error.c_str(); }
+
+nld_status features_from_image(const void* img, int32_t n1, int32_t n2, int32_t rho,
+                               int32_t with_pos, nld_prec prec, void* features, hipStream_t s) {
+  if (!img || !features) return fail(NLD_E_INVAL, "features_from_image: null pointer");
+  if (n1 < 1 || n2 < 1) return fail(NLD_E_INVAL, "features_from_image: image sides must be >= 1");
+  if (rho < 0 || rho > 15) return fail(NLD_E_INVAL, "features_from_image: rho must be in [0, 15]");
+  if (with_pos != 0 && with_pos != 1) return fail(NLD_E_INVAL, "features_from_image: with_pos must be 0 or 1");
+  if (prec != NLD_FP32 && prec != NLD_FP64) return fail(NLD_E_INVAL, "features_from_image: bad precision");
+  if ((long long)n1 * n2 > (1LL << 31) - 1) return fail(NLD_E_INVAL, "features_from_image: image too large");
+  return guarded("features_from_image", [&] {
+    nld::launch_features(img, n1, n2, rho, with_pos, prec, features, s);
+    return NLD_OK;
+  });
+}
+
+nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t d,
+                     const nld_kernel_desc* desc, hipStream_t s) {
+  if (!out || !features || !desc) return fail(NLD_E_INVAL, "nfft_plan: null pointer");
+  *out = nullptr;
+  if (N < 1) return fail(NLD_E_INVAL, "nfft_plan: N must be >= 1");
+  if (d < 1) return fail(NLD_E_INVAL, "nfft_plan: d must be >= 1");
+  const int L = desc->n_windows;
+  if (L < 1 || L > 1024) return fail(NLD_E_INVAL, "nfft_plan: n_windows must be in [1, 1024]");
+  if (!desc->win_dim || !desc->win_feat || !desc->sigma || !desc->weight)
+    return fail(NLD_E_INVAL, "nfft_plan: null window table");
+  if ((long long)N * L > 0x7fffffffLL) return fail(NLD_E_INVAL, "nfft_plan: N * n_windows too large");
+  if (desc->prec != NLD_FP32 && desc->prec != NLD_FP64) return fail(NLD_E_INVAL, "nfft_plan: bad precision");
+  int nf = 0;
+  for (int l = 0; l < L; ++l) {
+    if (desc->win_dim[l] < 1 || desc->win_dim[l] > 3)
+      return fail(NLD_E_INVAL, "nfft_plan: window dimension must be 1, 2 or 3");
+    nf += desc->win_dim[l];
+    if (!finite_pos(desc->sigma[l])) return fail(NLD_E_INVAL, "nfft_plan: sigma must be finite and > 0");
+    if (!std::isfinite(desc->weight[l]) || desc->weight[l] < 0.0)
+      return fail(NLD_E_INVAL, "nfft_plan: weights must be finite and >= 0");
+  }
+  for (int k = 0; k < nf; ++k)
+    if (desc->win_feat[k] < 0 || desc->win_feat[k] >= d)
+      return fail(NLD_E_INVAL, "nfft_plan: window feature index out of range");
+  auto bw_ok = [](int M) { return M == 0 || (M >= 8 && M <= 256 && M % 2 == 0); };
+  if (!bw_ok(desc->bandwidth)) return fail(NLD_E_INVAL, "nfft_plan: bandwidth must be 0 or even in [8, 256]");
+  if (desc->win_bandwidth)
+    for (int l = 0; l < L; ++l)
+      if (!bw_ok(desc->win_bandwidth[l]))
+        return fail(NLD_E_INVAL, "nfft_plan: window bandwidth must be 0 or even in [8, 256]");
+  if (desc->cutoff < 0 || desc->cutoff > 8) return fail(NLD_E_INVAL, "nfft_plan: cutoff must be in [0, 8]");
+  const double os = desc->oversampling == 0.0 ? 2.0 : desc->oversampling;
+  if (!std::isfinite(os) || os < 1.25 || os > 8.0)
+    return fail(NLD_E_INVAL, "nfft_plan: oversampling must be in [1.25, 8]");
+  const double tol = desc->matvec_tol == 0.0 ? 1e-6 : desc->matvec_tol;
+  if (!finite_pos(tol) || tol >= 1.0) return fail(NLD_E_INVAL, "nfft_plan: matvec_tol must be in (0, 1)");
+  nld_plan_s* h = nullptr;
+  nld_status st = guarded("nfft_plan", [&] {
+    h = new nld_plan_s();
+    nld::Plan& P = h->P;
+    P.prec = desc->prec;
+    P.N = N;
+    P.d = d;
+    P.L = L;
+    P.elem = desc->prec == NLD_FP32 ? 4 : 8;
+    P.win_dim.assign(desc->win_dim, desc->win_dim + L);
+    P.win_feat.assign(desc->win_feat, desc->win_feat + nf);
+    P.sigma.assign(desc->sigma, desc->sigma + L);
+    P.weight.assign(desc->weight, desc->weight + L);
+    P.bw.assign(L, desc->bandwidth);
+    if (desc->win_bandwidth)
+      for (int l = 0; l < L; ++l)
+        if (desc->win_bandwidth[l]) P.bw[l] = desc->win_bandwidth[l];
+    P.cutoff = desc->cutoff;
+    P.oversampling = os;
+    P.tol = tol;
+    NLD_HIP(hipHostMalloc((void**)&P.st_host, sizeof(nld::CgState), hipHostMallocDefault));
+    int dev = 0, lds = 65536;
+    NLD_HIP(hipGetDevice(&dev));
+    NLD_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    P.lds_limit = std::min<long long>(lds, 160 * 1024);
+    nld::build_plan(P, features, s);
+    return NLD_OK;
+  });
+  if (st != NLD_OK) {
+    if (h) {
+      nld::release_plan(h->P);
+      if (h->P.st_host) (void)hipHostFree(h->P.st_host);
+      delete h;
+    }
+    return st;
+  }
+  *out = h;
+  return NLD_OK;
+}
+
+nld_status nfft_plan_destroy(nfft_plan_t plan) {
+  if (!plan) return fail(NLD_E_INVAL, "nfft_plan_destroy: null plan");
+  nld::release_plan(plan->P);
+  if (plan->P.st_host) (void)hipHostFree(plan->P.st_host);
+  delete plan;
+  return NLD_OK;
+}
+
+nld_status nfft_plan_window_info(nfft_plan_t plan, int32_t l, nld_window_info* info) {
+  if (!plan || !info) return fail(NLD_E_INVAL, "nfft_plan_window_info: null pointer");
+  if (l < 0 || l >= plan->P.L) return fail(NLD_E_INVAL, "nfft_plan_window_info: window out of range");
+  *info = plan->P.info[l];
+  return NLD_OK;
+}
+
+nld_status nfft_plan_size(nfft_plan_t plan, int64_t* N, int32_t* L, nld_prec* prec) {
+  if (!plan) return fail(NLD_E_INVAL, "nfft_plan_size: null plan");
+  if (N) *N = plan->P.N;
+  if (L) *L = plan->P.L;
+  if (prec) *prec = plan->P.prec;
+  return NLD_OK;
+}
+
+nld_status degree_vector(nfft_plan_t plan, double* D, hipStream_t s) {
+  if (!plan || !D) return fail(NLD_E_INVAL, "degree_vector: null pointer");
+  return guarded("degree_vector", [&] {
+    nld::Plan& P = plan->P;
+    P.stream = s;
+    if (!P.have_D) {
+      nld::matvec(P, P.ones, P.D, nld::EPI_DEGREE, nullptr, s);
+      P.have_D = true;
+      nld::compute_max_eta(P, s);
+    }
+    NLD_HIP(hipMemcpyAsync(D, P.D, P.N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return NLD_OK;
+  });
+}
+
+nld_status anova_matvec(nfft_plan_t plan, const void* v, void* y, hipStream_t s) {
+  if (!plan || !v || !y) return fail(NLD_E_INVAL, "anova_matvec: null pointer");
+  return guarded("anova_matvec", [&] {
+    plan->P.stream = s;
+    nld::matvec(plan->P, v, y, nld::EPI_ANOVA, nullptr, s);
+    return NLD_OK;
+  });
+}
+
+nld_status laplacian_matvec(nfft_plan_t plan, const void* v, void* y, hipStream_t s) {
+  if (!plan || !v || !y) return fail(NLD_E_INVAL, "laplacian_matvec: null pointer");
+  return guarded("laplacian_matvec", [&] {
+    nld::Plan& P = plan->P;
+    P.stream = s;
+    if (!P.have_D) {
+      nld::matvec(P, P.ones, P.D, nld::EPI_DEGREE, nullptr, s);
+      P.have_D = true;
+      nld::compute_max_eta(P, s);
+    }
+    nld::matvec(P, v, y, nld::EPI_LAPLACIAN, nullptr, s);
+    return NLD_OK;
+  });
+}
+
+nld_status pcg_solve(nfft_plan_t plan, double alpha, const void* f, void* u,
+                     const nld_pcg_opts* opts, nld_pcg_info* info, hipStream_t s) {
+  if (!plan || !f || !u || !opts || !info) return fail(NLD_E_INVAL, "pcg_solve: null pointer");
+  if (!finite_pos(alpha)) return fail(NLD_E_INVAL, "pcg_solve: alpha must be finite and > 0");
+  if (!finite_pos(opts->tol) || opts->tol >= 1.0) return fail(NLD_E_INVAL, "pcg_solve: tol must be in (0, 1)");
+  if (opts->maxit < 0) return fail(NLD_E_INVAL, "pcg_solve: maxit must be >= 0");
+  if ((opts->precond != 0 && opts->precond != 1) || (opts->deflate != 0 && opts->deflate != 1) ||
+      (opts->use_u0 != 0 && opts->use_u0 != 1))
+    return fail(NLD_E_INVAL, "pcg_solve: precond, deflate and use_u0 must be 0 or 1");
+  std::memset(info, 0, sizeof(*info));
+  info->relres_true = -1.0;
+  nld_status result = NLD_OK;
+  nld_status st = guarded("pcg_solve", [&] {
+    plan->P.stream = s;
+    result = nld::run_pcg(plan->P, alpha, f, u, *opts, *info, s);
+    return NLD_OK;
+  });
+  if (st != NLD_OK) {
+    info->status = st;
+    return st;
+  }
+  if (result == NLD_E_NOCONV) nld::set_error("pcg_solve: maximum number of iterations reached");
+  if (result == NLD_E_BREAKDOWN) nld::set_error("pcg_solve: CG breakdown (non-finite or non-positive scalar)");
+  return result;
+}
+
+}  // extern "C"

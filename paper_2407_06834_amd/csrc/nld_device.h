@@ -1,0 +1,80 @@
+// Device helpers shared by the fast-summation and CG kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "nld_internal.h"
+
+namespace nld {
+
+// Scaled Kaiser-Bessel spreading weight at distance delta (grid cells, |delta| <= m):
+//   psi(delta) = m sinh(b z) / (z sinh(b m)),  z = sqrt(m^2 - delta^2),
+// evaluated as (m/z) exp(b (z - m)) (1 - exp(-2 b z)) / (1 - exp(-2 b m)), which does not
+// overflow; psi(0) = 1 and the z -> 0 limit is 2 b m exp(-b m) / (1 - exp(-2 b m)).
+__device__ __forceinline__ float kb_psi(float delta, float m, float b, float den) {
+  const float z2 = fmaxf(m * m - delta * delta, 0.0f);
+  const float z = sqrtf(z2);
+  if (z > 0.0f) return (m / z) * expf(b * (z - m)) * (-expm1f(-2.0f * b * z)) * den;
+  return 2.0f * b * m * expf(-b * m) * den;
+}
+__device__ __forceinline__ double kb_psi(double delta, double m, double b, double den) {
+  const double z2 = fmax(m * m - delta * delta, 0.0);
+  const double z = sqrt(z2);
+  if (z > 0.0) return (m / z) * exp(b * (z - m)) * (-expm1(-2.0 * b * z)) * den;
+  return 2.0 * b * m * exp(-b * m) * den;
+}
+
+// Deterministic FP64 reduction of NS values over the whole grid: every block reduces its
+// threads' values with a fixed tree, writes one partial per value, and the last block to
+// finish (agent-scope ticket) sums the partials in block order.  Returns true in the last
+// block, with the totals in out[] for every thread of that block.  Block size must be
+// kRedThreads; the ticket is reset by the last block.
+template <int NS>
+__device__ bool grid_reduce(const double (&v)[NS], double* red, unsigned* ticket,
+                            double (&out)[NS]) {
+  __shared__ double sh[NS][kRedThreads];
+  __shared__ int last;
+  const int t = threadIdx.x;
+  for (int k = 0; k < NS; ++k) sh[k][t] = v[k];
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if (t < s)
+      for (int k = 0; k < NS; ++k) sh[k][t] += sh[k][t + s];
+    __syncthreads();
+  }
+  if (t == 0) {
+    for (int k = 0; k < NS; ++k) red[(size_t)blockIdx.x * 8 + k] = sh[k][0];
+    __threadfence();
+    const unsigned prev = atomicAdd(ticket, 1u);
+    last = (prev == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double acc[NS];
+  for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+  for (unsigned b = t; b < gridDim.x; b += kRedThreads)
+    for (int k = 0; k < NS; ++k)
+      acc[k] += __hip_atomic_load(&red[(size_t)b * 8 + k], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  for (int k = 0; k < NS; ++k) sh[k][t] = acc[k];
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if (t < s)
+      for (int k = 0; k < NS; ++k) sh[k][t] += sh[k][t + s];
+    __syncthreads();
+  }
+  for (int k = 0; k < NS; ++k) out[k] = sh[k][0];
+  if (t == 0) atomicExch(ticket, 0u);
+  return true;
+}
+
+inline unsigned red_blocks(long long n) {
+  long long b = (n + kRedThreads - 1) / kRedThreads;
+  if (b > kRedBlocks) b = kRedBlocks;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+}  // namespace nld

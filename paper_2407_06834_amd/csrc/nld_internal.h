@@ -1,0 +1,153 @@
+// Internal declarations of libnld (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nld.h"
+
+namespace nld {
+
+constexpr int kMaxTap = 16;        // 2m for m <= 8
+constexpr int kRedBlocks = 512;    // blocks of the FP64 reductions
+constexpr int kRedThreads = 256;
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+struct HipError {
+  hipError_t err;
+  std::string where;
+};
+#define NLD_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess) throw ::nld::HipError{e_, std::string(#call)};           \
+  } while (0)
+
+// ------------------------------------------------------------------ per-window data
+// Every window is stored with three internal dimensions; a window with t kept dimensions
+// uses the last t of them and the leading ones have n = 1, a single tap of weight 1.
+struct WinDev {
+  int t;               // kept dimensions
+  int n[3];            // grid points per internal dimension
+  int taps[3];         // 2m, or 1 for an unused dimension
+  int m;
+  double b;            // Kaiser-Bessel shape
+  double kb_den;       // 1 / (1 - exp(-2 b m))
+  double weight;       // w_l
+  int ts[3], nts[3];   // tiles: extent and count per dimension
+  int pe[3];           // padded tile extent: ts + taps - 1
+  int tile_off;        // first global tile id of this window
+  long long grid_off;  // offset of this window's grid in the concatenated grid buffer
+  long long grid_size; // n0 n1 n2
+  const void* coef;    // [3][n_max] per-dimension Fourier multipliers (precision T)
+  int n_max;
+};
+
+struct TileJob {       // a chunk of the nodes of one tile (spreading and gathering)
+  int win, tile, pbeg, pend, slot;   // pbeg/pend: positions in the sorted node list
+};
+struct FoldJob {       // a range of grid cells of one window
+  int win, ncell;
+  long long cell0;
+};
+struct ConvJob {
+  int win;
+  int nl;              // lines in this job (<= lines per workgroup)
+  long long off;       // offset of the first element of the first line in the window grid
+};
+
+// FP64 state of one CG solve (device)
+struct CgState {
+  double alpha;        // system parameter alpha
+  double tol;          // relative tolerance
+  double wsum;         // sum_l w_l (eta = D - wsum)
+  double tol2_b2;      // tol^2 ||f_perp||^2
+  double bnorm2;       // ||f_perp||^2
+  double mean_f, mean_u0;
+  double rho, a, beta, mean_t, mean_q, mean_r;
+  double rr;           // ||r||^2 of the last update
+  double rr_true;      // true residual norm^2 (diagnostic)
+  double const_f;      // 0 if f is constant
+  double last_pq, last_rho;  // last <p, A p> and <r, s> (diagnostics)
+  double sum_pinv;     // sum_i 1 / P_i
+  int iters, maxit, done, status, precond, deflate;
+  unsigned int ticket[8];
+};
+
+// Host-side plan
+struct Plan {
+  nld_prec prec;
+  int64_t N;
+  int d;
+  int L;
+  int elem;                        // sizeof(T)
+  std::vector<int> win_dim, win_feat;
+  std::vector<double> sigma, weight;
+  std::vector<int> bw;             // requested bandwidth per window (0 = automatic)
+  int cutoff = 0;
+  double oversampling = 2.0;
+  double tol = 1e-6;
+  long long lds_limit = 65536;      // bytes of LDS a workgroup may use
+  std::vector<WinDev> wins;        // host copy
+  std::vector<nld_window_info> info;
+  std::vector<std::vector<double>> coef_host;  // per window [3][n_max]
+  hipStream_t stream = nullptr;
+
+  // device buffers
+  WinDev* d_wins = nullptr;
+  void* features = nullptr;        // not owned
+  int* g_idx = nullptr;            // nodes of every window sorted by tile: node index,
+  unsigned* g_base = nullptr;      // packed base cell and fractional offsets [3][L N]
+  void* g_frac = nullptr;
+  void* coef = nullptr;            // all windows' multipliers
+  void* grid = nullptr;            // concatenated grids
+  long long grid_total = 0;
+  void* padded = nullptr;          // padded tile accumulators, one slot per spreading job
+  long long slot_stride = 0;       // cells per slot
+  int* tile_slot0 = nullptr;       // first slot of each global tile, and slot count
+  int* tile_nslot = nullptr;
+  int n_tiles_total = 0;
+  void* ylocal = nullptr;          // [L][N] per-window results
+  double* D = nullptr;             // degree vector
+  double* sumv = nullptr;          // sum of the vector (windows without kept dimensions)
+  bool has_flat = false;           // some window has no kept dimension: K_l = 1 1^T
+  bool have_D = false;
+  double max_eta = 0.0;            // max(D) - sum_l w_l
+  void* ones = nullptr;            // vector of ones (precision T)
+  // schedules: tile jobs grouped by window dimension t (group g holds the jobs of t = g + 1)
+  TileJob* d_tjobs = nullptr;
+  int tjob_begin[4] = {0, 0, 0, 0};  // jobs of group g are [tjob_begin[g], tjob_begin[g + 1])
+  int max_padded = 1;              // largest padded tile (cells)
+  FoldJob* d_fjobs = nullptr; int n_fjobs = 0;
+  ConvJob* d_conv[3] = {nullptr, nullptr, nullptr}; int n_conv[3] = {0, 0, 0};
+  int conv_lines[3] = {0, 0, 0};   // lines per conv workgroup for each axis pass
+  // CG work vectors (precision T) and FP64 scratch
+  void* z = nullptr; void* r = nullptr; void* p = nullptr; void* q = nullptr;
+  double* red = nullptr;           // reduction partials [kRedBlocks][8]
+  CgState* st = nullptr;           // device CG state
+  CgState* st_host = nullptr;      // pinned mirror
+};
+
+// ------------------------------------------------------------------ launchers
+// plan construction (plan.hip)
+void build_plan(Plan& P, const void* features, hipStream_t s);
+void release_plan(Plan& P);
+void launch_features(const void* img, int n1, int n2, int rho, int with_pos, nld_prec prec,
+                     void* F, hipStream_t s);
+
+// fast summation (nfft.hip)
+enum Epilogue { EPI_ANOVA = 0, EPI_LAPLACIAN = 1, EPI_DEGREE = 2, EPI_CG_Q = 3, EPI_CG_INIT = 4,
+                EPI_CG_TRUE = 5 };
+// Runs the per-window fast summations on v and the window reduction with the epilogue.
+void matvec(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hipStream_t s);
+
+// CG (pcg.hip)
+void compute_max_eta(Plan& P, hipStream_t s);
+nld_status run_pcg(Plan& P, double alpha, const void* f, void* u, const nld_pcg_opts& o,
+                   nld_pcg_info& info, hipStream_t s);
+
+}  // namespace nld

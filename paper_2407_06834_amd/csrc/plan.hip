@@ -1,0 +1,688 @@
+// Plan construction: features, per-window torus scaling, grid coordinates, stable radix sort
+// of the nodes by grid tile, work schedules.  (Paper Sec. 3: NFFT fast Gauss summation; the
+// parameter choices follow the NFFT literature the paper cites and are listed in the design
+// notes of the repository.)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <stdexcept>
+
+#include "nld_internal.h"
+
+namespace nld {
+
+namespace {
+
+constexpr int kTileChunk = 2048;     // nodes per spreading / gathering workgroup
+
+template <typename T>
+__global__ void k_features(const T* __restrict__ img, int n1, int n2, int rho, int with_pos,
+                           T* __restrict__ F) {
+  const long long N = (long long)n1 * n2;
+  const int P = 2 * rho + 1;
+  const int d = (with_pos ? 2 : 0) + P * P;
+  const long long total = N * d;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / N);
+    const long long i = idx - (long long)k * N;
+    const int row = (int)(i / n2), col = (int)(i - (long long)row * n2);
+    T val;
+    if (with_pos && k == 0) {
+      val = (T)((double)col / (double)n2);
+    } else if (with_pos && k == 1) {
+      val = (T)((double)row / (double)n1);
+    } else {
+      const int p = k - (with_pos ? 2 : 0);
+      const int r = row + p / P - rho, c = col + p % P - rho;
+      val = (r >= 0 && r < n1 && c >= 0 && c < n2) ? img[(long long)r * n2 + c] : (T)0;
+    }
+    F[idx] = val;
+  }
+}
+
+// Per-block min / max of selected feature rows; partials [ncol][nblk][2].
+template <typename T>
+__global__ void k_minmax(const T* __restrict__ F, long long N, const int* __restrict__ cols,
+                         double* __restrict__ part) {
+  const int c = blockIdx.y;
+  const T* x = F + (long long)cols[c] * N;
+  double lo = INFINITY, hi = -INFINITY;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = (double)x[i];
+    lo = fmin(lo, v);
+    hi = fmax(hi, v);
+  }
+  __shared__ double slo[256], shi[256];
+  slo[threadIdx.x] = lo;
+  shi[threadIdx.x] = hi;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      slo[threadIdx.x] = fmin(slo[threadIdx.x], slo[threadIdx.x + s]);
+      shi[threadIdx.x] = fmax(shi[threadIdx.x], shi[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((long long)c * gridDim.x + blockIdx.x) * 2 + 0] = slo[0];
+    part[((long long)c * gridDim.x + blockIdx.x) * 2 + 1] = shi[0];
+  }
+}
+
+struct CoordParams {
+  int feat[3];        // feature row per internal dimension (-1: unused)
+  double centre[3], scale[3];
+  int n[3], m;
+  int ts[3], nts[3];
+  unsigned tile_off;
+};
+
+__device__ inline int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
+
+// Grid coordinates of every (window, node): packed base cell, fractional offsets and the
+// global key of the tile that holds the base cell.
+template <typename T>
+__global__ void k_coords(const T* __restrict__ F, long long N, int L,
+                         const CoordParams* __restrict__ cp, unsigned* __restrict__ base,
+                         T* __restrict__ frac, unsigned* __restrict__ key) {
+  const long long total = N * L;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const int l = (int)(idx / N);
+    const long long j = idx - (long long)l * N;
+    const CoordParams p = cp[l];
+    int b[3];
+    for (int dd = 0; dd < 3; ++dd) {
+      T fr = (T)0;
+      int bi = 0;
+      if (p.feat[dd] >= 0) {
+        const double x = (double)F[(long long)p.feat[dd] * N + j];
+        const double xt = __dmul_rn(x - p.centre[dd], p.scale[dd]);
+        const double u = __dadd_rn(__dmul_rn((double)p.n[dd], xt), 0.5 * p.n[dd]);
+        const double fl = floor(u);
+        bi = (int)fl;
+        fr = (T)(u - fl);
+        if (fr >= (T)1) { fr = (T)0; bi += 1; }
+        bi = ((bi % p.n[dd]) + p.n[dd]) % p.n[dd];
+      }
+      b[dd] = bi;
+      frac[((long long)l * 3 + dd) * N + j] = fr;
+    }
+    base[idx] = (unsigned)b[0] | ((unsigned)b[1] << 8) | ((unsigned)b[2] << 16);
+    const int g = ((b[0] / p.ts[0]) * p.nts[1] + b[1] / p.ts[1]) * p.nts[2] + b[2] / p.ts[2];
+    key[idx] = p.tile_off + (unsigned)g;
+  }
+}
+
+// First position of every key in the sorted key array (lower bound), for keys 0..nkeys.
+__global__ void k_key_offsets(const unsigned* __restrict__ keys, long long n, int nkeys,
+                              unsigned* __restrict__ off) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > nkeys) return;
+  long long lo = 0, hi = n;
+  while (lo < hi) {
+    const long long mid = (lo + hi) >> 1;
+    if (keys[mid] < (unsigned)k) lo = mid + 1;
+    else hi = mid;
+  }
+  off[k] = (unsigned)lo;
+}
+
+// ---------------------------------------------------------------- exclusive scan (uint32)
+constexpr int kScanThreads = 256, kScanPer = 8, kScanBlock = kScanThreads * kScanPer;
+
+__global__ void k_scan_local(unsigned* __restrict__ data, long long n, unsigned* __restrict__ sums) {
+  __shared__ unsigned s[kScanThreads];
+  const long long b0 = (long long)blockIdx.x * kScanBlock + (long long)threadIdx.x * kScanPer;
+  unsigned v[kScanPer];
+  unsigned tsum = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = (b0 + k < n) ? data[b0 + k] : 0u;
+    tsum += v[k];
+  }
+  s[threadIdx.x] = tsum;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const unsigned add = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  unsigned run = s[threadIdx.x] - tsum;   // exclusive prefix of this thread
+  for (int k = 0; k < kScanPer; ++k) {
+    if (b0 + k < n) data[b0 + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = s[kScanThreads - 1];
+}
+
+__global__ void k_scan_add(unsigned* __restrict__ data, long long n, const unsigned* __restrict__ sums) {
+  const unsigned add = sums[blockIdx.x];
+  const long long b0 = (long long)blockIdx.x * kScanBlock;
+  for (int k = threadIdx.x; k < kScanBlock; k += kScanThreads)
+    if (b0 + k < n) data[b0 + k] += add;
+}
+
+template <typename P>
+P* dalloc(long long count, hipStream_t s) {
+  void* p = nullptr;
+  if (count <= 0) count = 1;
+  hipError_t e = hipMallocAsync(&p, (size_t)count * sizeof(P), s);
+  if (e != hipSuccess) throw HipError{e, "hipMallocAsync"};
+  return (P*)p;
+}
+inline void dfree(void* p, hipStream_t s) {
+  if (p) (void)hipFreeAsync(p, s);
+}
+
+void exclusive_scan(unsigned* data, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  const long long nb = (n + kScanBlock - 1) / kScanBlock;
+  unsigned* sums = dalloc<unsigned>(nb, s);
+  hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, sums);
+  NLD_HIP(hipGetLastError());
+  if (nb > 1) {
+    exclusive_scan(sums, nb, s);
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, sums);
+    NLD_HIP(hipGetLastError());
+  }
+  dfree(sums, s);
+}
+
+// ---------------------------------------------------------------- stable LSD radix sort
+// 8-bit digits, one wave of 64 lanes per block and 1024 items per block.  Within a block
+// the items are ranked in order with wave ballots, so equal keys keep their input order.
+constexpr int kSortLanes = 64, kSortRounds = 16, kSortItems = kSortLanes * kSortRounds;
+
+__global__ void __launch_bounds__(kSortLanes)
+k_radix_hist(const unsigned* __restrict__ keys, long long n, int shift, unsigned* __restrict__ hist,
+             int nblk) {
+  __shared__ unsigned h[256];
+  for (int i = threadIdx.x; i < 256; i += kSortLanes) h[i] = 0;
+  __syncthreads();
+  const long long b0 = (long long)blockIdx.x * kSortItems;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const long long i = b0 + r * kSortLanes + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  for (int dgt = threadIdx.x; dgt < 256; dgt += kSortLanes)
+    hist[(long long)dgt * nblk + blockIdx.x] = h[dgt];
+}
+
+__global__ void __launch_bounds__(kSortLanes)
+k_radix_scatter(const unsigned* __restrict__ kin, const unsigned* __restrict__ vin,
+                unsigned* __restrict__ kout, unsigned* __restrict__ vout, long long n, int shift,
+                const unsigned* __restrict__ offs, int nblk) {
+  __shared__ unsigned cur[256];
+  for (int dgt = threadIdx.x; dgt < 256; dgt += kSortLanes)
+    cur[dgt] = offs[(long long)dgt * nblk + blockIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const long long b0 = (long long)blockIdx.x * kSortItems;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const long long i = b0 + r * kSortLanes + lane;
+    const bool valid = i < n;
+    const unsigned key = valid ? kin[i] : 0u;
+    const unsigned dg = (key >> shift) & 255u;
+    unsigned long long mask = __ballot(valid);
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool set = (dg >> bit) & 1u;
+      const unsigned long long bal = __ballot(set);
+      mask &= set ? bal : ~bal;
+    }
+    const unsigned rank = (unsigned)__popcll(mask & below);
+    const unsigned group = (unsigned)__popcll(mask);
+    unsigned dst = 0;
+    if (valid) dst = cur[dg] + rank;
+    __syncthreads();
+    if (valid) {
+      kout[dst] = key;
+      vout[dst] = vin[i];
+      if (rank == group - 1) cur[dg] += group;
+    }
+    __syncthreads();
+  }
+}
+
+// Sorts (keys, vals) by the low key_bits bits of keys, stably.  Result in keys / vals.
+void radix_sort_pairs(unsigned* keys, unsigned* vals, long long n, int key_bits, hipStream_t s) {
+  if (n <= 1) return;
+  const int nblk = (int)((n + kSortItems - 1) / kSortItems);
+  unsigned* k2 = dalloc<unsigned>(n, s);
+  unsigned* v2 = dalloc<unsigned>(n, s);
+  unsigned* hist = dalloc<unsigned>(256LL * nblk, s);
+  unsigned *ka = keys, *va = vals, *kb = k2, *vb = v2;
+  const int passes = std::max(1, (key_bits + 7) / 8);
+  for (int pss = 0; pss < passes; ++pss) {
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortLanes), 0, s, ka, n, 8 * pss, hist, nblk);
+    NLD_HIP(hipGetLastError());
+    exclusive_scan(hist, 256LL * nblk, s);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortLanes), 0, s, ka, va, kb, vb, n,
+                       8 * pss, hist, nblk);
+    NLD_HIP(hipGetLastError());
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (ka != keys) {
+    NLD_HIP(hipMemcpyAsync(keys, ka, n * sizeof(unsigned), hipMemcpyDeviceToDevice, s));
+    NLD_HIP(hipMemcpyAsync(vals, va, n * sizeof(unsigned), hipMemcpyDeviceToDevice, s));
+  }
+  dfree(k2, s);
+  dfree(v2, s);
+  dfree(hist, s);
+}
+
+// Copy the coordinates of sorted entries: out[e] = in[(window of e, node of e)].
+template <typename T>
+__global__ void k_gather_entries(const unsigned* __restrict__ vals, long long n, long long N,
+                                 const unsigned* __restrict__ base, const T* __restrict__ frac,
+                                 int* __restrict__ out_idx, unsigned* __restrict__ out_base,
+                                 T* __restrict__ out_frac, long long out_stride) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const unsigned flat = vals[e];
+    const long long l = flat / N, j = flat - l * N;
+    out_idx[e] = (int)j;
+    out_base[e] = base[flat];
+    for (int dd = 0; dd < 3; ++dd) out_frac[dd * out_stride + e] = frac[(l * 3 + dd) * N + j];
+  }
+}
+
+__global__ void k_iota(unsigned* __restrict__ x, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] = (unsigned)i;
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, long long n, T val) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] = val;
+}
+
+inline unsigned grid_for(long long n, int threads = 256) {
+  long long b = (n + threads - 1) / threads;
+  return (unsigned)std::max<long long>(1, std::min<long long>(b, 65536));
+}
+
+// ---------------------------------------------------------------- host math for the plan
+double compression(double sigma, double R, int M) {
+  const double q = 2.0 * M_PI * M * sigma * sigma / (R * R);
+  return (std::sqrt(1.0 + q) - 1.0) / q;
+}
+
+// Fourier factor carried by the spreading grid for frequency k (scaled Kaiser-Bessel window:
+// pi m I0(m sqrt(b^2 - (2 pi k / n)^2)) / sinh(b m)).
+double kb_fourier(double k, int n, int m, double b) {
+  const double x = m * std::sqrt(b * b - std::pow(2.0 * M_PI * k / n, 2));
+  return M_PI * m * std::cyl_bessel_i(0.0, x) / std::sinh(b * m);
+}
+
+int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Per-entry error estimate of the band-limited periodic kernel in one dimension.
+double dim_error(double sigma, double R, int M) {
+  const double a = compression(sigma, R, M);
+  const double st = 2.0 * a * sigma / R;
+  return std::exp(-std::pow(M_PI * st * M / 2.0, 2));
+}
+
+}  // namespace
+
+void launch_features(const void* img, int n1, int n2, int rho, int with_pos, nld_prec prec,
+                     void* F, hipStream_t s) {
+  const long long total = (long long)n1 * n2 * ((with_pos ? 2 : 0) + (2 * rho + 1) * (2 * rho + 1));
+  if (prec == NLD_FP32)
+    hipLaunchKernelGGL(k_features<float>, dim3(grid_for(total)), dim3(256), 0, s,
+                       (const float*)img, n1, n2, rho, with_pos, (float*)F);
+  else
+    hipLaunchKernelGGL(k_features<double>, dim3(grid_for(total)), dim3(256), 0, s,
+                       (const double*)img, n1, n2, rho, with_pos, (double*)F);
+  NLD_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
+  const long long N = P.N;
+  const int L = P.L;
+  // ---- 1. data range of every feature row used by a window
+  std::vector<int> cols(P.win_feat);
+  std::sort(cols.begin(), cols.end());
+  cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+  const int ncol = (int)cols.size();
+  const int nblk = (int)std::min<long long>(256, (N + 255) / 256);
+  int* d_cols = dalloc<int>(ncol, s);
+  double* d_part = dalloc<double>(2LL * ncol * nblk, s);
+  NLD_HIP(hipMemcpyAsync(d_cols, cols.data(), ncol * sizeof(int), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_minmax<T>, dim3(nblk, ncol), dim3(256), 0, s, (const T*)features, N, d_cols,
+                     d_part);
+  NLD_HIP(hipGetLastError());
+  std::vector<double> part(2LL * ncol * nblk);
+  NLD_HIP(hipMemcpyAsync(part.data(), d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  NLD_HIP(hipStreamSynchronize(s));
+  dfree(d_cols, s);
+  dfree(d_part, s);
+  std::vector<double> lo(P.d, 0.0), hi(P.d, 0.0);
+  for (int c = 0; c < ncol; ++c) {
+    double a = INFINITY, b = -INFINITY;
+    for (int k = 0; k < nblk; ++k) {
+      a = std::min(a, part[(c * nblk + k) * 2]);
+      b = std::max(b, part[(c * nblk + k) * 2 + 1]);
+    }
+    if (!std::isfinite(a) || !std::isfinite(b))
+      throw std::invalid_argument("features contain non-finite values");
+    lo[cols[c]] = a;
+    hi[cols[c]] = b;
+  }
+
+  // ---- 2. per-window parameters
+  const bool fp32 = (P.prec == NLD_FP32);
+  std::vector<CoordParams> cp(L);
+  P.wins.assign(L, WinDev{});
+  P.info.assign(L, nld_window_info{});
+  P.coef_host.assign(L, {});
+  unsigned tile_total = 0;
+  long long max_padded = 1;
+  long long grid_total = 0;
+  int n_max = 1;
+  int off = 0;
+  for (int l = 0; l < L; ++l) {
+    const int dl = P.win_dim[l];
+    std::vector<int> kept;
+    std::vector<double> R;
+    for (int k = 0; k < dl; ++k) {
+      const int c = P.win_feat[off + k];
+      const double r = hi[c] - lo[c];
+      if (r > 0.0) {
+        kept.push_back(c);
+        R.push_back(r);
+      }
+    }
+    off += dl;
+    const int t = (int)kept.size();
+    const double sigma = P.sigma[l];
+    // bandwidth M
+    int M = P.bw[l];
+    if (M == 0) {
+      static const int cand[] = {16, 24, 32, 48, 64, 96, 128};
+      M = 128;
+      for (int c : cand) {
+        double e = 0.0;
+        for (double r : R) e = std::max(e, dim_error(sigma, r, c));
+        if (e <= 1e-2 * P.tol) { M = c; break; }
+      }
+    }
+    int m = P.cutoff;
+    if (m == 0) m = fp32 ? 4 : (P.tol >= 1e-9 ? 6 : 8);
+    int n = next_pow2((int)std::ceil(P.oversampling * M - 1e-9));
+    n = std::max(n, 32);
+    if (n <= M) n = next_pow2(M + 1);
+    if (n > 256) throw std::invalid_argument("grid larger than 256 points per dimension");
+    if (2 * m > n / 2) throw std::invalid_argument("cutoff too large for the grid");
+    const double b = M_PI * (2.0 - (double)M / n);
+    WinDev& w = P.wins[l];
+    w.t = t;
+    w.m = m;
+    w.b = b;
+    w.kb_den = 1.0 / (-std::expm1(-2.0 * b * m));
+    w.weight = P.weight[l];
+    CoordParams& p = cp[l];
+    p.m = m;
+    nld_window_info& inf = P.info[l];
+    inf.dims_kept = t;
+    inf.bandwidth = M;
+    inf.grid = n;
+    inf.cutoff = m;
+    std::vector<double> coef(3LL * n, 0.0);
+    for (int dd = 0; dd < 3; ++dd) {
+      const int k = dd - (3 - t);   // kept-dimension index of internal dim dd
+      if (k >= 0) {
+        const int c = kept[k];
+        const double a = compression(sigma, R[k], M);
+        const double sc = 2.0 * a / R[k];
+        const double st = sigma * sc;
+        p.feat[dd] = c;
+        p.centre[dd] = 0.5 * (lo[c] + hi[c]);
+        p.scale[dd] = sc;
+        p.n[dd] = n;
+        w.n[dd] = n;
+        w.taps[dd] = 2 * m;
+        inf.compression[k] = a;
+        inf.lo[k] = lo[c];
+        inf.hi[k] = hi[c];
+        for (int q = 0; q < n; ++q) {
+          const int kf = (q < n / 2) ? q : q - n;
+          if (std::abs(kf) <= M / 2 - 1) {
+            const double bh = std::sqrt(M_PI) * st * std::exp(-std::pow(M_PI * st * kf, 2));
+            const double ph = kb_fourier(kf, n, m, b);
+            coef[(long long)dd * n + q] = bh / (ph * ph);
+          }
+        }
+      } else {
+        p.feat[dd] = -1;
+        p.centre[dd] = 0.0;
+        p.scale[dd] = 0.0;
+        p.n[dd] = 1;
+        w.n[dd] = 1;
+        w.taps[dd] = 1;
+      }
+    }
+    // tiles: the padded tile (tile + 2m - 1 halo cells per dimension) must fit in LDS
+    int tsz;
+    if (t == 3) {
+      // the spreading accumulates the padded tile in FP64
+      tsz = 16;
+      if (const char* e = std::getenv("NLD_TILE3")) tsz = std::atoi(e);
+      while (tsz > 8 && (long long)std::pow(tsz + 2 * m - 1, 3) * 8LL > P.lds_limit) tsz /= 2;
+    } else if (t == 2) {
+      tsz = std::min(64, n);
+    } else {
+      tsz = n;
+    }
+    if (t > 0 && (tsz < m || n % tsz != 0)) throw std::invalid_argument("no tile size fits the cutoff");
+    long long padded = 1;
+    for (int dd = 0; dd < 3; ++dd) {
+      const int ts = (w.n[dd] == 1) ? 1 : std::min(tsz, w.n[dd]);
+      w.ts[dd] = p.ts[dd] = ts;
+      w.nts[dd] = p.nts[dd] = w.n[dd] / ts;
+      w.pe[dd] = ts + w.taps[dd] - 1;
+      padded *= w.pe[dd];
+    }
+    if (padded * 8LL > P.lds_limit)
+      throw std::invalid_argument("padded tile does not fit in LDS");
+    max_padded = std::max<long long>(max_padded, padded);
+    p.tile_off = tile_total;
+    w.tile_off = (int)tile_total;
+    tile_total += (unsigned)(w.nts[0] * w.nts[1] * w.nts[2]);
+    w.grid_off = grid_total;
+    w.grid_size = (long long)w.n[0] * w.n[1] * w.n[2];
+    grid_total += w.grid_size;
+    n_max = std::max(n_max, n);
+    P.coef_host[l] = coef;
+  }
+  // coefficient tables, stride n_max per dimension
+  std::vector<T> coef_all(3LL * n_max * L, (T)0);
+  for (int l = 0; l < L; ++l) {
+    const int n = P.info[l].grid;
+    for (int dd = 0; dd < 3; ++dd)
+      for (int q = 0; q < n; ++q)
+        coef_all[((long long)l * 3 + dd) * n_max + q] = (T)P.coef_host[l][(long long)dd * n + q];
+  }
+  P.coef = dalloc<T>((long long)coef_all.size(), s);
+  NLD_HIP(hipMemcpyAsync(P.coef, coef_all.data(), coef_all.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  for (int l = 0; l < L; ++l) {
+    P.wins[l].coef = (const T*)P.coef + (long long)l * 3 * n_max;
+    P.wins[l].n_max = n_max;
+  }
+
+  // ---- 3. coordinates of every (window, node)
+  const long long LN = N * L;
+  CoordParams* d_cp = dalloc<CoordParams>(L, s);
+  NLD_HIP(hipMemcpyAsync(d_cp, cp.data(), L * sizeof(CoordParams), hipMemcpyHostToDevice, s));
+  unsigned* base = dalloc<unsigned>(LN, s);
+  T* frac = dalloc<T>(3 * LN, s);
+  unsigned* key = dalloc<unsigned>(LN, s);
+  hipLaunchKernelGGL(k_coords<T>, dim3(grid_for(LN)), dim3(256), 0, s, (const T*)features, N, L, d_cp,
+                     base, frac, key);
+  NLD_HIP(hipGetLastError());
+
+  // ---- 4. nodes of every window sorted (stably) by tile; tile offsets by binary search
+  unsigned* val = dalloc<unsigned>(LN, s);
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(LN)), dim3(256), 0, s, val, LN);
+  NLD_HIP(hipGetLastError());
+  int kbits = 1;
+  while ((1u << kbits) < tile_total) ++kbits;
+  radix_sort_pairs(key, val, LN, kbits, s);
+  P.g_idx = dalloc<int>(LN, s);
+  P.g_base = dalloc<unsigned>(LN, s);
+  P.g_frac = dalloc<T>(3 * LN, s);
+  hipLaunchKernelGGL(k_gather_entries<T>, dim3(grid_for(LN)), dim3(256), 0, s, val, LN, N, base,
+                     frac, P.g_idx, P.g_base, (T*)P.g_frac, LN);
+  NLD_HIP(hipGetLastError());
+  unsigned* toff = dalloc<unsigned>(tile_total + 1, s);
+  hipLaunchKernelGGL(k_key_offsets, dim3((tile_total + 256) / 256), dim3(256), 0, s, key, LN,
+                     (int)tile_total, toff);
+  NLD_HIP(hipGetLastError());
+  std::vector<unsigned> ht(tile_total + 1);
+  NLD_HIP(hipMemcpyAsync(ht.data(), toff, (tile_total + 1) * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  NLD_HIP(hipStreamSynchronize(s));
+  if (ht[tile_total] != (unsigned)LN) throw std::runtime_error("internal: tile offsets do not add up");
+
+  // ---- 5. schedules (host): chunks of the nodes of every non-empty tile, grouped by t;
+  // every chunk owns one padded-tile slot; the fold sums a tile's slots in order.
+  std::vector<TileJob> jobs;
+  std::vector<int> slot0(tile_total, 0), nslot(tile_total, 0);
+  int slots = 0;
+  for (int g = 0; g < 3; ++g) {
+    P.tjob_begin[g] = (int)jobs.size();
+    for (int l = 0; l < L; ++l) {
+      const WinDev& w = P.wins[l];
+      if (w.t != g + 1) continue;      // windows without kept dimensions need no grid
+      const int nt = w.nts[0] * w.nts[1] * w.nts[2];
+      for (int tl = 0; tl < nt; ++tl) {
+        const unsigned gt = (unsigned)w.tile_off + tl;
+        const long long b0 = ht[gt], b1 = ht[gt + 1];
+        if (b1 == b0) continue;
+        slot0[gt] = slots;
+        for (long long c = b0; c < b1; c += kTileChunk) {
+          jobs.push_back(TileJob{l, tl, (int)c, (int)std::min(b1, c + kTileChunk), slots});
+          ++slots;
+          ++nslot[gt];
+        }
+      }
+    }
+  }
+  P.tjob_begin[3] = (int)jobs.size();
+  P.d_tjobs = dalloc<TileJob>(std::max<size_t>(1, jobs.size()), s);
+  NLD_HIP(hipMemcpyAsync(P.d_tjobs, jobs.data(), jobs.size() * sizeof(TileJob), hipMemcpyHostToDevice, s));
+  P.n_tiles_total = (int)tile_total;
+  P.tile_slot0 = dalloc<int>(tile_total, s);
+  P.tile_nslot = dalloc<int>(tile_total, s);
+  NLD_HIP(hipMemcpyAsync(P.tile_slot0, slot0.data(), tile_total * sizeof(int), hipMemcpyHostToDevice, s));
+  NLD_HIP(hipMemcpyAsync(P.tile_nslot, nslot.data(), tile_total * sizeof(int), hipMemcpyHostToDevice, s));
+  P.max_padded = (int)max_padded;
+  P.slot_stride = max_padded;
+  P.padded = dalloc<T>((long long)std::max(1, slots) * max_padded, s);
+  // fold jobs: 256 grid cells each
+  std::vector<FoldJob> fj;
+  for (int l = 0; l < L; ++l)
+    for (long long c = 0; P.wins[l].t > 0 && c < P.wins[l].grid_size; c += 256)
+      fj.push_back(FoldJob{l, (int)std::min<long long>(256, P.wins[l].grid_size - c), c});
+  P.n_fjobs = (int)fj.size();
+  P.d_fjobs = dalloc<FoldJob>(std::max<size_t>(1, fj.size()), s);
+  NLD_HIP(hipMemcpyAsync(P.d_fjobs, fj.data(), fj.size() * sizeof(FoldJob), hipMemcpyHostToDevice, s));
+
+  // convolution jobs: for each axis, lines of every window that has that axis; 16 lines per
+  // workgroup (8 for the largest FP64 grids, to keep the LDS footprint near 32 KB)
+  const int kConvLines = (n_max * (int)sizeof(T) >= 2048) ? 8 : 16;
+  for (int ax = 0; ax < 3; ++ax) {
+    std::vector<ConvJob> cjobs;
+    for (int l = 0; l < L; ++l) {
+      const WinDev& w = P.wins[l];
+      if (w.n[ax] == 1) continue;
+      const int n0 = w.n[0], n1 = w.n[1], n2 = w.n[2];
+      if (ax == 2) {
+        const long long lines = (long long)n0 * n1;
+        for (long long q = 0; q < lines; q += kConvLines)
+          cjobs.push_back(ConvJob{l, (int)std::min<long long>(kConvLines, lines - q), q * n2});
+      } else if (ax == 1) {
+        for (int i0 = 0; i0 < n0; ++i0)
+          for (int i2 = 0; i2 < n2; i2 += kConvLines)
+            cjobs.push_back(ConvJob{l, std::min(kConvLines, n2 - i2), (long long)i0 * n1 * n2 + i2});
+      } else {
+        for (int i1 = 0; i1 < n1; ++i1)
+          for (int i2 = 0; i2 < n2; i2 += kConvLines)
+            cjobs.push_back(ConvJob{l, std::min(kConvLines, n2 - i2), (long long)i1 * n2 + i2});
+      }
+    }
+    P.n_conv[ax] = (int)cjobs.size();
+    P.conv_lines[ax] = kConvLines;
+    if (!cjobs.empty()) {
+      P.d_conv[ax] = dalloc<ConvJob>(cjobs.size(), s);
+      NLD_HIP(hipMemcpyAsync(P.d_conv[ax], cjobs.data(), cjobs.size() * sizeof(ConvJob),
+                             hipMemcpyHostToDevice, s));
+    }
+  }
+
+  // ---- 7. work buffers
+  P.grid_total = grid_total;
+  P.grid = dalloc<T>(grid_total, s);
+  P.ylocal = dalloc<T>(LN, s);
+  P.D = dalloc<double>(N, s);
+  P.sumv = dalloc<double>(1, s);
+  P.has_flat = false;
+  for (const auto& w : P.wins) P.has_flat = P.has_flat || (w.t == 0);
+  P.ones = dalloc<T>(N, s);
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(N)), dim3(256), 0, s, (T*)P.ones, N, (T)1);
+  NLD_HIP(hipGetLastError());
+  P.z = dalloc<T>(N, s);
+  P.r = dalloc<T>(N, s);
+  P.p = dalloc<T>(N, s);
+  P.q = dalloc<T>(N, s);
+  P.red = dalloc<double>((long long)kRedBlocks * 8, s);
+  P.st = dalloc<CgState>(1, s);
+  hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(256), 0, s, (unsigned char*)P.st,
+                     (long long)sizeof(CgState), (unsigned char)0);
+  NLD_HIP(hipGetLastError());
+  P.d_wins = dalloc<WinDev>(L, s);
+  NLD_HIP(hipMemcpyAsync(P.d_wins, P.wins.data(), L * sizeof(WinDev), hipMemcpyHostToDevice, s));
+
+  dfree(d_cp, s);
+  dfree(base, s);
+  dfree(frac, s);
+  dfree(key, s);
+  dfree(val, s);
+  dfree(toff, s);
+  NLD_HIP(hipStreamSynchronize(s));
+  P.have_D = false;
+}
+
+void build_plan(Plan& P, const void* features, hipStream_t s) {
+  P.features = const_cast<void*>(features);
+  P.stream = s;
+  if (P.prec == NLD_FP32) build_plan_t<float>(P, features, s);
+  else build_plan_t<double>(P, features, s);
+}
+
+void release_plan(Plan& P) {
+  hipStream_t s = P.stream;
+  void* bufs[] = {P.d_wins, P.g_idx, P.g_base, P.g_frac, P.coef, P.grid, P.padded, P.tile_slot0,
+                  P.tile_nslot, P.ylocal, P.D, P.sumv, P.ones, P.d_tjobs, P.d_fjobs, P.d_conv[0], P.d_conv[1],
+                  P.d_conv[2], P.z, P.r, P.p, P.q, P.red, P.st};
+  for (void* b : bufs) dfree(b, s);
+  (void)hipStreamSynchronize(s);
+}
+
+}  // namespace nld

@@ -1,0 +1,273 @@
+"""Thin ctypes binding of libnld (C ABI in include/nld.h).  Argument marshalling only: every
+step of the computation runs in the library's HIP kernels.  PyTorch supplies device memory
+and the current stream.
+
+The functions mirror the C entry points (nfft_plan, nfft_plan_destroy, degree_vector,
+anova_matvec, laplacian_matvec, pcg_solve, features_from_image); ``Plan`` wraps a plan
+handle for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnld.so")
+
+NLD_OK, NLD_E_INVAL, NLD_E_NOMEM, NLD_E_HIP, NLD_E_NOCONV, NLD_E_BREAKDOWN, NLD_E_STATE = range(7)
+NLD_FP32, NLD_FP64 = 0, 1
+STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NOCONV", 5: "E_BREAKDOWN",
+                6: "E_STATE"}
+
+# Entry points declared in include/nld.h
+SYMBOLS = ("nfft_plan", "nfft_plan_destroy", "nfft_plan_window_info", "nfft_plan_size",
+           "degree_vector", "anova_matvec", "laplacian_matvec", "pcg_solve",
+           "features_from_image", "nld_last_error")
+
+
+class KernelDesc(ctypes.Structure):
+    _fields_ = [("n_windows", ctypes.c_int32), ("win_dim", ctypes.POINTER(ctypes.c_int32)),
+                ("win_feat", ctypes.POINTER(ctypes.c_int32)),
+                ("sigma", ctypes.POINTER(ctypes.c_double)),
+                ("weight", ctypes.POINTER(ctypes.c_double)), ("bandwidth", ctypes.c_int32),
+                ("win_bandwidth", ctypes.POINTER(ctypes.c_int32)), ("cutoff", ctypes.c_int32),
+                ("oversampling", ctypes.c_double), ("matvec_tol", ctypes.c_double),
+                ("prec", ctypes.c_int32)]
+
+
+class WindowInfo(ctypes.Structure):
+    _fields_ = [("dims_kept", ctypes.c_int32), ("bandwidth", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("cutoff", ctypes.c_int32),
+                ("compression", ctypes.c_double * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3)]
+
+
+class PcgOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("use_u0", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("deflate", ctypes.c_int32),
+                ("true_residual", ctypes.c_int32), ("timing", ctypes.c_int32)]
+
+
+class PcgInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("relres_rec", ctypes.c_double),
+                ("relres_true", ctypes.c_double), ("kappa_est", ctypes.c_double),
+                ("ms_solve", ctypes.c_double), ("ms_matvec", ctypes.c_double),
+                ("matvecs_timed", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "relres_rec": self.relres_rec,
+                "relres_true": self.relres_true, "kappa_est": self.kappa_est,
+                "ms_solve": self.ms_solve, "ms_matvec": self.ms_matvec,
+                "matvecs_timed": self.matvecs_timed,
+                "status": STATUS_NAMES.get(self.status, self.status)}
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libnld.so from the package directory; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libnld.so not found at {LIB_PATH}; run "
+                          "`python -m paper_2407_06834_amd.build` (or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "nfft_plan": [ctypes.POINTER(P), P, I64, I32, ctypes.POINTER(KernelDesc), P],
+        "nfft_plan_destroy": [P],
+        "nfft_plan_window_info": [P, I32, ctypes.POINTER(WindowInfo)],
+        "nfft_plan_size": [P, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I32)],
+        "degree_vector": [P, P, P],
+        "anova_matvec": [P, P, P, P],
+        "laplacian_matvec": [P, P, P, P],
+        "pcg_solve": [P, D, P, P, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo), P],
+        "features_from_image": [P, I32, I32, I32, I32, I32, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.nld_last_error.argtypes = []
+    lib.nld_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class NldError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status: int):
+    if status != NLD_OK:
+        raise NldError(status, load().nld_last_error().decode())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dtype(prec: int):
+    return torch.float32 if prec == NLD_FP32 else torch.float64
+
+
+def _vec(t: torch.Tensor, n: int, dtype, name: str):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.numel() == n):
+        raise ValueError(f"{name}: expected a contiguous {dtype} CUDA tensor with {n} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def features_from_image(img: torch.Tensor, rho: int, with_pos: bool = True, stream=None):
+    """SoA features (d, N) of a 2-D image tensor (float32 or float64, on the GPU)."""
+    if img.dim() != 2 or not img.is_cuda or img.dtype not in (torch.float32, torch.float64):
+        raise ValueError("img: expected a 2-D float32/float64 CUDA tensor")
+    img = img.contiguous()
+    n1, n2 = img.shape
+    prec = NLD_FP32 if img.dtype == torch.float32 else NLD_FP64
+    d = (2 if with_pos else 0) + (2 * rho + 1) ** 2
+    F = torch.empty((d, n1 * n2), dtype=img.dtype, device=img.device)
+    _check(load().features_from_image(ctypes.c_void_p(img.data_ptr()), n1, n2, rho,
+                                      1 if with_pos else 0, prec, ctypes.c_void_p(F.data_ptr()),
+                                      _stream(stream)))
+    return F
+
+
+@dataclass
+class WindowParams:
+    dims_kept: int
+    bandwidth: int
+    grid: int
+    cutoff: int
+    compression: tuple
+    lo: tuple
+    hi: tuple
+
+
+class Plan:
+    """A plan of the fast ANOVA summation over fixed features (see nfft_plan in nld.h)."""
+
+    def __init__(self, features: torch.Tensor, windows, sigma, weight, bandwidth: int = 0,
+                 cutoff: int = 0, oversampling: float = 2.0, matvec_tol: float = 1e-6,
+                 win_bandwidth=None, stream=None):
+        lib = load()
+        if features.dim() != 2 or not features.is_cuda:
+            raise ValueError("features: expected a (d, N) CUDA tensor")
+        if features.dtype not in (torch.float32, torch.float64):
+            raise ValueError("features: float32 or float64")
+        self.features = features.contiguous()   # kept alive with the plan
+        self.prec = NLD_FP32 if features.dtype == torch.float32 else NLD_FP64
+        self.dtype = features.dtype
+        self.d, self.N = self.features.shape
+        L = len(windows)
+        self.L = L
+        self._wd = (ctypes.c_int32 * L)(*[len(w) for w in windows])
+        flat = [int(c) for w in windows for c in w]
+        self._wf = (ctypes.c_int32 * max(1, len(flat)))(*flat)
+        self._sig = (ctypes.c_double * L)(*[float(s) for s in sigma])
+        self._wt = (ctypes.c_double * L)(*[float(w) for w in weight])
+        self._wbw = (ctypes.c_int32 * L)(*win_bandwidth) if win_bandwidth is not None else None
+        desc = KernelDesc(L, self._wd, self._wf, self._sig, self._wt, int(bandwidth),
+                          self._wbw if self._wbw is not None else None, int(cutoff),
+                          float(oversampling), float(matvec_tol), self.prec)
+        h = ctypes.c_void_p()
+        _check(lib.nfft_plan(ctypes.byref(h), ctypes.c_void_p(self.features.data_ptr()), self.N,
+                             self.d, ctypes.byref(desc), _stream(stream)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().nfft_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def window_info(self, l: int) -> WindowParams:
+        info = WindowInfo()
+        _check(load().nfft_plan_window_info(self.handle, l, ctypes.byref(info)))
+        t = info.dims_kept
+        return WindowParams(t, info.bandwidth, info.grid, info.cutoff,
+                            tuple(info.compression[:t]), tuple(info.lo[:t]), tuple(info.hi[:t]))
+
+    def degree_vector(self, stream=None) -> torch.Tensor:
+        D = torch.empty(self.N, dtype=torch.float64, device=self.features.device)
+        _check(load().degree_vector(self.handle, ctypes.c_void_p(D.data_ptr()), _stream(stream)))
+        return D
+
+    def anova_matvec(self, v: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+        out = torch.empty_like(v) if out is None else out
+        _check(load().anova_matvec(self.handle, _vec(v, self.N, self.dtype, "v"),
+                                   _vec(out, self.N, self.dtype, "out"), _stream(stream)))
+        return out
+
+    def laplacian_matvec(self, v: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+        out = torch.empty_like(v) if out is None else out
+        _check(load().laplacian_matvec(self.handle, _vec(v, self.N, self.dtype, "v"),
+                                       _vec(out, self.N, self.dtype, "out"), _stream(stream)))
+        return out
+
+    def pcg_solve(self, alpha: float, f: torch.Tensor, u0: torch.Tensor | None = None,
+                  tol: float = 1e-6, maxit: int = 500, precond: bool = True,
+                  deflate: bool = True, true_residual: bool = False, out=None, stream=None,
+                  raise_on_noconv: bool = False, timing: bool = False):
+        """Solve (I + alpha L~) u = f.  Returns (u, info dict)."""
+        u = torch.empty_like(f) if out is None else out
+        if u0 is not None:
+            u.copy_(u0)
+        opts = PcgOpts(float(tol), int(maxit), 1 if u0 is not None else 0, int(bool(precond)),
+                       int(bool(deflate)), int(bool(true_residual)), int(bool(timing)))
+        info = PcgInfo()
+        st = load().pcg_solve(self.handle, float(alpha), _vec(f, self.N, self.dtype, "f"),
+                              _vec(u, self.N, self.dtype, "u"), ctypes.byref(opts),
+                              ctypes.byref(info), _stream(stream))
+        if st not in (NLD_OK, NLD_E_NOCONV, NLD_E_BREAKDOWN) or (raise_on_noconv and st != NLD_OK):
+            _check(st)
+        return u, info.as_dict()
+
+
+def nfft_plan(features, windows, sigma, weight, **kw) -> Plan:
+    return Plan(features, windows, sigma, weight, **kw)
+
+
+def nfft_plan_destroy(plan: Plan):
+    plan.close()
+
+
+def degree_vector(plan: Plan, **kw):
+    return plan.degree_vector(**kw)
+
+
+def anova_matvec(plan: Plan, v, out=None, **kw):
+    return plan.anova_matvec(v, out=out, **kw)
+
+
+def laplacian_matvec(plan: Plan, v, out=None, **kw):
+    return plan.laplacian_matvec(v, out=out, **kw)
+
+
+def pcg_solve(plan: Plan, alpha, f, **kw):
+    return plan.pcg_solve(alpha, f, **kw)
+
+
+def window_table(rho: int, with_pos: bool = True):
+    """Fixed window grouping of the feature rows (position + centre first, then the other
+    patch offsets in raster order in chunks of three)."""
+    P = 2 * rho + 1
+    base = 2 if with_pos else 0
+    centre = base + rho * P + rho
+    rest = [base + p for p in range(P * P) if not (with_pos and base + p == centre)]
+    wins = [[0, 1, centre]] if with_pos else []
+    wins += [rest[s:s + 3] for s in range(0, len(rest), 3)]
+    return wins

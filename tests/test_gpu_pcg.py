@@ -1,0 +1,116 @@
+"""GPU parity of the deflated Jacobi PCG solve (HIP path vs the oracle)."""
+import numpy as np
+import pytest
+
+from gpu_util import rel, torch_gpu
+from oracle import kernel as K
+from oracle import nfft as ON
+from oracle import solve as OS
+from oracle.features import features_from_image as o_features
+from paper_2407_06834_amd.synth import make_image
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(n1, n2, rho, seed, dtype, sig, M, m, wts=None, noise=0.1):
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    _, f = make_image(seed, n1, n2, 6, 4, noise)
+    img = torch.tensor(f, dtype=dtype, device="cuda")
+    F = nld.features_from_image(img, rho)
+    wins = nld.window_table(rho)
+    wts = wts or [1.0] * len(wins)
+    plan = nld.Plan(F, wins, sig, wts, bandwidth=M, cutoff=m)
+    return torch, nld, f, img, F, wins, wts, plan
+
+
+def test_config1_solve_matches_dense_cholesky():
+    # 64 x 64, 3x3 patch + position, sigma 0.1, alpha 0.5, M = 64 (parity bandwidth), m = 6
+    torch, nld, f, img, F, wins, wts, plan = _problem(64, 64, 1, 0, torch_gpu().float64,
+                                                      [0.1] * 4, 64, 6)
+    u, info = plan.pcg_solve(0.5, img.reshape(-1), tol=1e-10, maxit=200, true_residual=True)
+    assert info["status"] == "OK" and info["relres_rec"] <= 1e-10
+    F64 = o_features(f, 1)
+    W = K.anova_dense(F64, wins, [0.1] * 4, wts)
+    us = OS.dense_solve(K.system_dense(W, 0.5), f.reshape(-1))
+    assert rel(u.cpu().numpy(), us) < 1e-6
+    assert info["relres_true"] < 1e-9
+    assert abs(float(u.mean()) - f.mean()) < 1e-13
+
+
+def test_config1_iterates_match_oracle_pcg():
+    torch, nld, f, img, F, wins, wts, plan = _problem(32, 32, 1, 0, torch_gpu().float64,
+                                                      [0.1] * 4, 64, 6)
+    F64 = o_features(f, 1)
+    fv = f.reshape(-1)
+
+    def W_nfft(v):
+        y = np.zeros_like(v)
+        for l, w in enumerate(wins):
+            p = plan.window_info(l)
+            y += ON.fast_gauss_window(F64[w], v, 0.1, p.bandwidth, p.grid, p.cutoff)
+        return y
+    D = W_nfft(np.ones(fv.size))
+    eta = D - 4.0
+    op = OS.system_operator(W_nfft, D, 0.5)
+    uo, it_o, rr_o, _ = OS.pcg_projector(op, fv, eta, 0.5, 1e-10, 200)
+    u, info = plan.pcg_solve(0.5, img.reshape(-1), tol=1e-10, maxit=200)
+    assert abs(info["iters"] - it_o) <= 1
+    assert rel(u.cpu().numpy(), uo) < 1e-9
+    ub, it_b, _, _ = OS.pcg_ubasis(op, fv, eta, 0.5, 1e-10, 200)
+    assert abs(info["iters"] - it_b) <= 1
+
+
+@pytest.mark.parametrize("alpha", [0.1, 10.0])
+def test_fp32_solve_close_to_fp64(alpha):
+    torch = torch_gpu()
+    t64 = _problem(48, 48, 1, 2, torch.float64, [0.1] * 4, 64, 8)
+    t32 = _problem(48, 48, 1, 2, torch.float32, [0.1] * 4, 64, 4)
+    u64, i64 = t64[7].pcg_solve(alpha, t64[3].reshape(-1), tol=1e-10)
+    u32, i32 = t32[7].pcg_solve(alpha, t32[3].reshape(-1), tol=1e-6)
+    assert i64["status"] == "OK" and i32["status"] == "OK"
+    assert rel(u32.double().cpu().numpy(), u64.cpu().numpy()) < 1e-4
+
+
+def test_deflated_iterations_flat_plain_cg_grows():
+    torch, nld, f, img, F, wins, wts, plan = _problem(40, 40, 1, 4, torch_gpu().float64,
+                                                      [0.1] * 4, 64, 6)
+    fv = img.reshape(-1)
+    its = []
+    for alpha in (1e2, 1e4, 1e6):
+        _, info = plan.pcg_solve(alpha, fv, tol=1e-8, maxit=500)
+        assert info["status"] == "OK"
+        its.append(info["iters"])
+    _, plain = plan.pcg_solve(1e6, fv, tol=1e-8, maxit=2000, precond=False, deflate=False)
+    assert max(its) - min(its) <= 6
+    assert plain["iters"] > 2 * its[-1]
+
+
+def test_constant_image_zero_iterations():
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    img = torch.full((20, 24), 0.37, dtype=torch.float64, device="cuda")
+    F = nld.features_from_image(img, 1)
+    plan = nld.Plan(F, nld.window_table(1), [0.1] * 4, [1.0] * 4, bandwidth=32, cutoff=4)
+    u, info = plan.pcg_solve(1.0, img.reshape(-1), tol=1e-8)
+    assert info["iters"] == 0 and info["status"] == "OK"
+    assert torch.equal(u, img.reshape(-1))
+
+
+def test_maxit_returns_noconv_and_last_iterate():
+    torch, nld, f, img, F, wins, wts, plan = _problem(32, 32, 1, 5, torch_gpu().float64,
+                                                      [0.1] * 4, 32, 4)
+    u, info = plan.pcg_solve(5.0, img.reshape(-1), tol=1e-12, maxit=1)
+    assert info["status"] == "E_NOCONV" and info["iters"] == 1
+    assert torch.isfinite(u).all()
+    assert abs(float(u.mean()) - f.mean()) < 1e-12
+
+
+def test_warm_start_from_solution_converges_immediately():
+    torch, nld, f, img, F, wins, wts, plan = _problem(32, 32, 1, 6, torch_gpu().float64,
+                                                      [0.1] * 4, 32, 6)
+    fv = img.reshape(-1)
+    u, info = plan.pcg_solve(1.0, fv, tol=1e-11)
+    u2, info2 = plan.pcg_solve(1.0, fv, u0=u, tol=1e-9)
+    assert info2["iters"] <= 1
+    assert rel(u2.cpu().numpy(), u.cpu().numpy()) < 1e-9
