@@ -39,36 +39,51 @@ __device__ __forceinline__ int tile_origin(const WinDev& w, int tile, int dd) {
   return tt * w.ts[dd];
 }
 
-// Weights of the W = 2m taps of one node in one dimension: tap i sits at cell b - m + 1 + i,
-// at distance fr + m - 1 - i from the node.
-template <typename T, int W>
-__device__ __forceinline__ void tap_row(T fr, T b, T den, T* wt) {
-  constexpr int m = W / 2;
+
+// ---------------------------------------------------------------------------- window polynomial
+template <typename T, int K>
+__device__ __forceinline__ T horner(const T* c, T x) {
+  T r = c[K - 1];
 #pragma unroll
-  for (int i = 0; i < W; ++i) wt[i] = kb_psi(fr + (T)(m - 1 - i), (T)m, b, den);
+  for (int k = K - 2; k >= 0; --k) r = r * x + c[k];
+  return r;
+}
+
+__device__ __forceinline__ unsigned lane_bcast(unsigned v, int q) {
+  return (unsigned)__builtin_amdgcn_readlane((int)v, q);
+}
+__device__ __forceinline__ float lane_bcast(float v, int q) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+}
+__device__ __forceinline__ double lane_bcast(double v, int q) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), q);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), q);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Weights of the W = 2m taps of one node in one dimension (tap i at cell floor(u) - m + 1 + i,
+// distance fr + m - 1 - i): the per-tap window polynomials evaluated at x = 2 fr - 1.
+template <typename T, int W>
+__device__ __forceinline__ void poly_row(const T* psi, T fr, T* wt) {
+  constexpr int K = PsiDeg<T>::value + 1;
+  const T x = (T)2 * fr - (T)1;
+#pragma unroll
+  for (int i = 0; i < W; ++i) wt[i] = horner<T, K>(psi + i * K, x);
 }
 
 // ---------------------------------------------------------------------------- spreading
-// One workgroup of kSpreadWaves wavefronts per chunk of a tile's nodes.  The chunk's taps are
-// accumulated in LDS over the padded tile (tile plus the 2m - 1 halo cells its nodes' taps
-// reach) and written to the chunk's slot; the fold kernel adds the slots covering each grid
-// cell.  Every wavefront visits all nodes of the chunk but only adds the taps that fall in its
-// own slab of the padded tile along the first kept dimension, so no two wavefronts touch the
-// same LDS cell and the accumulation order is fixed: results are reproducible.  Within a
-// wavefront, lane l walks the taps of its node in an order rotated by l, so lanes whose nodes
-// share a grid cell (common: neighbouring pixels with equal features) hit different cells.
-template <typename T, int W>
-__device__ __forceinline__ void rotated_taps(T fr, T b, T den, int rot, T* wt, int* off) {
-  constexpr int m = W / 2;
-#pragma unroll
-  for (int k = 0; k < W; ++k) {
-    int i = k + rot;
-    i = (i >= W) ? i - W : i;
-    off[k] = i;
-    wt[k] = kb_psi(fr + (T)(m - 1 - i), (T)m, b, den);
-  }
-}
-
+// One workgroup (4 wavefronts) per chunk (<= 2048) of a tile's nodes, which the plan sorted by
+// tile and then by cell, so nodes sharing a grid cell are consecutive ("runs").  A wavefront
+// walks its quarter of the chunk one node at a time; lane l owns the tap pair (i1, i2) of the
+// last two kept dimensions and keeps the 2m taps of the first kept dimension in registers, so a
+// run of r nodes costs one set of LDS additions instead of r.  When the cell changes the
+// registers are added into the padded tile (tile plus the 2m - 1 halo cells the taps reach) as
+// 64-bit fixed-point integers scaled by 2^(61 - e), 2^e <= sum |v| over the chunk: integer
+// addition is exact and associative, so the result does not depend on the order in which the
+// wavefronts add (reproducible), and ds_add_u64 is fast where LDS float atomics are not.
+// The slot is then written back in the working precision; the fold kernel sums the slots that
+// cover each grid cell.
 template <typename T, int W, int TD>
 __global__ void __launch_bounds__(kSpreadThreads)
 k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int job0,
@@ -76,78 +91,150 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
          const T* __restrict__ g_frac, long long LN, const T* __restrict__ v,
          T* __restrict__ padded, long long slot_stride, const CgState* __restrict__ st) {
   if (st && st->done) return;
+  constexpr int K = PsiDeg<T>::value + 1;
+  constexpr int PAIRS = (TD == 1) ? W : W * W;
+  constexpr int NP = (PAIRS + 63) / 64;
+  constexpr int NI0 = (TD == 3) ? W : 1;
+  constexpr bool REG = (NP * K * 2 * (int)sizeof(T) / 4) <= 72;
   extern __shared__ unsigned char smem_raw[];
-  // FP64 accumulators in both precisions: LDS float atomics are far slower than double ones
-  double* acc = reinterpret_cast<double*>(smem_raw);
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem_raw);
+  __shared__ double s_part[kSpreadWaves];
+  __shared__ T s_psi[REG ? 1 : W * K];
   const TileJob job = jobs[job0 + blockIdx.x];
   const WinDev& w = wins[job.win];
-  const int pe0 = w.pe[0], pe1 = w.pe[1], pe2 = w.pe[2];
-  const int cells = pe0 * pe1 * pe2;
-  for (int c = threadIdx.x; c < cells; c += kSpreadThreads) acc[c] = 0.0;
-  __syncthreads();
-  constexpr int m = W / 2;
-  constexpr int OD = 3 - TD;                       // first kept (outer) dimension
+  const int pe1 = w.pe[1], pe2 = w.pe[2];
+  const int cells = w.pe[0] * pe1 * pe2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int pe_out = w.pe[OD];
-  const int own_lo = (wave * pe_out) / kSpreadWaves, own_hi = ((wave + 1) * pe_out) / kSpreadWaves;
-  const int o_out = tile_origin(w, job.tile, OD);
-  const int o1 = tile_origin(w, job.tile, 1), o2 = tile_origin(w, job.tile, 2);
-  const T b = (T)w.b, den = (T)w.kb_den;
-  const int r2 = lane % W, r1 = (lane / W) % W, r0 = lane % W;
-  for (int p = job.pbeg + lane; p < job.pend; p += 64) {
-    const unsigned bb = g_base[p];
-    const int l_out = (int)((bb >> (8 * OD)) & 255u) - o_out;
-    // taps along the outer dimension that land in this wave's slab: local l_out + i
-    const int i_lo = max(0, own_lo - l_out), i_hi = min(W, own_hi - l_out);
-    if (i_lo >= i_hi) continue;
-    const T vj = v[g_idx[p]];
-    if (vj == (T)0) continue;
-    const T fr_out = g_frac[(long long)OD * LN + p];
-    const int span = i_hi - i_lo;
-    if constexpr (TD == 1) {
-      for (int k = 0; k < span; ++k) {
-        int i = i_lo + (k + r0) % span;
-        atomicAdd(&acc[l_out + i], (double)(vj * kb_psi(fr_out + (T)(m - 1 - i), (T)m, b, den)));
-      }
-    } else {
-      const int l2 = (int)((bb >> 16) & 255u) - o2;
-      T w2[W];
-      int c2[W];
-      rotated_taps<T, W>(g_frac[2 * LN + p], b, den, r2, w2, c2);
-      if constexpr (TD == 2) {
-        for (int k = 0; k < span; ++k) {
-          const int i = i_lo + (k + r1) % span;
-          const T c1 = vj * kb_psi(fr_out + (T)(m - 1 - i), (T)m, b, den);
-          double* row = acc + (l_out + i) * pe2 + l2;
+  const T* psi = reinterpret_cast<const T*>(w.psi);
+  for (int c = threadIdx.x; c < cells; c += kSpreadThreads) acc[c] = 0ull;
+  if constexpr (!REG)
+    for (int c = threadIdx.x; c < W * K; c += kSpreadThreads) s_psi[c] = psi[c];
+  // fixed-point scale of this chunk
+  double sa = 0.0;
+  for (int p = job.pbeg + threadIdx.x; p < job.pend; p += kSpreadThreads)
+    sa += fabs((double)v[g_idx[p]]);
+  for (int off = 32; off > 0; off >>= 1) sa += __shfl_xor(sa, off);
+  if (lane == 0) s_part[wave] = sa;
+  __syncthreads();
+  double tot = 0.0;
+  for (int k = 0; k < kSpreadWaves; ++k) tot += s_part[k];
+  T* out = padded + (long long)job.slot * slot_stride;
+  if (!(tot > 0.0)) {
+    for (int c = threadIdx.x; c < cells; c += kSpreadThreads) out[c] = (T)0;
+    return;
+  }
+  const double scale = ldexp(1.0, 61 - ilogb(tot));
+  // this lane's tap pairs and their window polynomials
+  int i1[NP], i2[NP];
+  bool pv[NP];
+  T c1[REG ? NP : 1][REG ? K : 1], c2[REG ? NP : 1][REG ? K : 1], c0[K];
 #pragma unroll
-          for (int k2 = 0; k2 < W; ++k2) atomicAdd(&row[c2[k2]], (double)(c1 * w2[k2]));
-        }
-      } else {
-        const int l1 = (int)((bb >> 8) & 255u) - o1;
-        T w1[W];
-        int c1i[W];
-        rotated_taps<T, W>(g_frac[LN + p], b, den, r1, w1, c1i);
-        for (int k = 0; k < span; ++k) {
-          const int i = i_lo + (k + r0) % span;
-          const T c0 = vj * kb_psi(fr_out + (T)(m - 1 - i), (T)m, b, den);
-          double* plane = acc + ((l_out + i) * pe1 + l1) * pe2 + l2;
+  for (int k = 0; k < NP; ++k) {
+    const int t = lane + 64 * k;
+    pv[k] = t < PAIRS;
+    const int tt = pv[k] ? t : 0;
+    i1[k] = (TD == 1) ? 0 : tt / W;
+    i2[k] = (TD == 1) ? tt : tt % W;
+    if constexpr (REG) {
 #pragma unroll
-          for (int k1 = 0; k1 < W; ++k1) {
-            const T cc1 = c0 * w1[k1];
-            double* row = plane + c1i[k1] * pe2;
-#pragma unroll
-            for (int k2 = 0; k2 < W; ++k2) atomicAdd(&row[c2[k2]], (double)(cc1 * w2[k2]));
-          }
-        }
+      for (int q = 0; q < K; ++q) {
+        c2[k][q] = psi[i2[k] * K + q];
+        c1[k][q] = (TD >= 2) ? psi[i1[k] * K + q] : (T)0;
       }
     }
   }
+  if constexpr (TD == 3) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) c0[q] = psi[(lane % W) * K + q];
+  }
+  if constexpr (!REG) __syncthreads();
+  const int o0 = tile_origin(w, job.tile, 0), o1 = tile_origin(w, job.tile, 1),
+            o2 = tile_origin(w, job.tile, 2);
+  T accr[NP][NI0];
+#pragma unroll
+  for (int k = 0; k < NP; ++k)
+#pragma unroll
+    for (int i = 0; i < NI0; ++i) accr[k][i] = (T)0;
+  constexpr unsigned kNone = 0xffffffffu;
+  unsigned cur = kNone;
+  auto flush = [&]() {
+    const int l0 = (int)(cur & 255u) - o0, l1 = (int)((cur >> 8) & 255u) - o1,
+              l2 = (int)((cur >> 16) & 255u) - o2;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      if (!pv[k]) continue;
+#pragma unroll
+      for (int i = 0; i < NI0; ++i) {
+        int cell;
+        if constexpr (TD == 3) cell = ((l0 + i) * pe1 + l1 + i1[k]) * pe2 + l2 + i2[k];
+        else if constexpr (TD == 2) cell = (l1 + i1[k]) * pe2 + l2 + i2[k];
+        else cell = l2 + i2[k];
+        const long long qv = __double2ll_rn((double)accr[k][i] * scale);
+        atomicAdd(&acc[cell], (unsigned long long)qv);
+        accr[k][i] = (T)0;
+      }
+    }
+  };
+  const int npts = job.pend - job.pbeg;
+  const int per = (npts + kSpreadWaves - 1) / kSpreadWaves;
+  const int q0 = job.pbeg + wave * per, q1 = min(job.pend, q0 + per);
+  for (int base_p = q0; base_p < q1; base_p += 64) {
+    const int p = base_p + lane;
+    const bool ok = p < q1;
+    const unsigned mb = ok ? g_base[p] : 0u;
+    const T f0 = (ok && TD == 3) ? g_frac[p] : (T)0;
+    const T f1 = (ok && TD >= 2) ? g_frac[LN + p] : (T)0;
+    const T f2 = ok ? g_frac[2 * LN + p] : (T)0;
+    const T vv = ok ? v[g_idx[p]] : (T)0;
+    const int cnt = min(64, q1 - base_p);
+    for (int q = 0; q < cnt; ++q) {
+      const unsigned bq = lane_bcast(mb, q);
+      if (bq != cur) {
+        if (cur != kNone) flush();
+        cur = bq;
+      }
+      const T vq = lane_bcast(vv, q);
+      const T x2 = (T)2 * lane_bcast(f2, q) - (T)1;
+      const T x1 = (T)2 * lane_bcast(f1, q) - (T)1;
+      T w12[NP];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        T a2, a1 = (T)1;
+        if constexpr (REG) {
+          a2 = horner<T, K>(c2[k], x2);
+          if constexpr (TD >= 2) a1 = horner<T, K>(c1[k], x1);
+        } else {
+          a2 = horner<T, K>(s_psi + i2[k] * K, x2);
+          if constexpr (TD >= 2) a1 = horner<T, K>(s_psi + i1[k] * K, x1);
+        }
+        w12[k] = vq * a1 * a2;
+      }
+      if constexpr (TD == 3) {
+        const T x0 = (T)2 * lane_bcast(f0, q) - (T)1;
+        const T p0 = horner<T, K>(c0, x0);          // tap (lane % W) of the first dimension
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+          const T s0 = lane_bcast(p0, i);
+#pragma unroll
+          for (int k = 0; k < NP; ++k) accr[k][i] += w12[k] * s0;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) accr[k][0] += w12[k];
+      }
+    }
+  }
+  if (cur != kNone) flush();
   __syncthreads();
-  T* out = padded + (long long)job.slot * slot_stride;
-  for (int c = threadIdx.x; c < cells; c += kSpreadThreads) out[c] = (T)acc[c];
+  const double inv = 1.0 / scale;
+  for (int c = threadIdx.x; c < cells; c += kSpreadThreads)
+    out[c] = (T)((double)(long long)acc[c] * inv);
 }
 
-// Grid cell value = sum of the padded-tile slots that cover the cell, in fixed order.
+// Fold: every grid cell sums, in fixed order, the padded-tile slots that cover it.  Along each
+// dimension a cell at local offset x of its tile is covered by the left neighbour if x < m
+// (padded index x + ts + m - 1), by its own tile (index x + m - 1) and by the right neighbour if
+// x > ts - m (index x - ts + m - 1); tile sizes are powers of two, so only shifts and masks.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_fold(const WinDev* __restrict__ wins, const FoldJob* __restrict__ jobs,
@@ -158,44 +245,107 @@ k_fold(const WinDev* __restrict__ wins, const FoldJob* __restrict__ jobs,
   if ((int)threadIdx.x >= job.ncell) return;
   const WinDev& w = wins[job.win];
   const long long c = job.cell0 + threadIdx.x;
-  int cc[3];
-  cc[2] = (int)(c % w.n[2]);
-  cc[1] = (int)((c / w.n[2]) % w.n[1]);
-  cc[0] = (int)(c / ((long long)w.n[2] * w.n[1]));
-  // up to three (tile, local index) candidates per dimension, in the order left, home, right
-  int ct[3][3], cl[3][3];
-  bool ok[3][3];
-#pragma unroll
-  for (int dd = 0; dd < 3; ++dd) {
-    const int ts = w.ts[dd];
-    // taps reach m - 1 cells to the left of a tile and m cells to the right
-    const int left = (w.taps[dd] > 1) ? w.m - 1 : 0;
-    const int home = cc[dd] / ts;
+  int ct[3][3], cl[3][3], cn[3];
+  {
+    const int n12 = w.n[1] * w.n[2];
+    int cc[3];
+    cc[0] = (int)(c / n12);
+    const int r = (int)(c - (long long)cc[0] * n12);
+    cc[1] = r / w.n[2];
+    cc[2] = r - cc[1] * w.n[2];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const int tu = home + k - 1;
-      const int li = cc[dd] - tu * ts + left;
-      ok[dd][k] = (li >= 0 && li < w.pe[dd]);
-      ct[dd][k] = ((tu % w.nts[dd]) + w.nts[dd]) % w.nts[dd];
-      cl[dd][k] = li;
+      const int ts = w.ts[k], lts = w.lts[k], mask = w.nts[k] - 1;
+      const int left = (w.taps[k] > 1) ? w.m - 1 : 0;
+      const int x = cc[k] & (ts - 1), home = cc[k] >> lts;
+      int q = 0;
+      if (w.taps[k] > 1 && x < w.m) {             // left neighbour's halo
+        ct[k][q] = (home - 1) & mask;
+        cl[k][q] = x + ts + left;
+        ++q;
+      }
+      ct[k][q] = home;
+      cl[k][q] = x + left;
+      ++q;
+      if (w.taps[k] > 1 && x > ts - w.m) {        // right neighbour's halo
+        ct[k][q] = (home + 1) & mask;
+        cl[k][q] = x - ts + left;
+        ++q;
+      }
+      cn[k] = q;
     }
   }
+  const int pe1 = w.pe[1], pe2 = w.pe[2];
   T sum = (T)0;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int bq = 0; bq < 3; ++bq)
-#pragma unroll
-      for (int e = 0; e < 3; ++e) {
-        if (!(ok[0][a] && ok[1][bq] && ok[2][e])) continue;
-        const int gt = w.tile_off + (ct[0][a] * w.nts[1] + ct[1][bq]) * w.nts[2] + ct[2][e];
+  for (int a = 0; a < cn[0]; ++a)
+    for (int bq = 0; bq < cn[1]; ++bq)
+      for (int e = 0; e < cn[2]; ++e) {
+        const int gt = w.tile_off + (((ct[0][a] << w.lnts[1]) + ct[1][bq]) << w.lnts[2]) + ct[2][e];
         const int ns = tile_nslot[gt];
         if (ns == 0) continue;
-        const long long pidx = ((long long)cl[0][a] * w.pe[1] + cl[1][bq]) * w.pe[2] + cl[2][e];
+        const long long pidx = ((long long)cl[0][a] * pe1 + cl[1][bq]) * pe2 + cl[2][e];
         const T* src = padded + (long long)tile_slot0[gt] * slot_stride + pidx;
-        for (int q = 0; q < ns; ++q) sum += src[(long long)q * slot_stride];
+        for (int k = 0; k < ns; ++k) sum += src[(long long)k * slot_stride];
       }
   grid[w.grid_off + c] = sum;
+}
+
+// Fold of a 3-D window, one workgroup per tile of TS^3 cells: thread (x1, x2) owns a column of
+// TS cells along the first dimension in registers and adds, neighbour by neighbour (fixed
+// order) and slot by slot, the padded-tile values that fall on its column.  Consecutive threads
+// read consecutive padded cells; no barriers, no LDS.
+template <typename T, int TS>
+__global__ void __launch_bounds__(TS * TS)
+k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs,
+        const T* __restrict__ padded, long long slot_stride, const int* __restrict__ tile_slot0,
+        const int* __restrict__ tile_nslot, T* __restrict__ grid, const CgState* __restrict__ st) {
+  if (st && st->done) return;
+  const Fold3Job job = jobs[blockIdx.x];
+  const WinDev& w = wins[job.win];
+  const int x2 = threadIdx.x % TS, x1 = threadIdx.x / TS;
+  const int tc2 = job.tile & (w.nts[2] - 1);
+  const int tc1 = (job.tile >> w.lnts[2]) & (w.nts[1] - 1);
+  const int tc0 = job.tile >> (w.lnts[2] + w.lnts[1]);
+  const int left = w.m - 1, pe = w.pe[0];
+  const long long pe2 = pe, pe12 = (long long)pe * pe;
+  T acc[TS];
+#pragma unroll
+  for (int k = 0; k < TS; ++k) acc[k] = (T)0;
+  for (int d0 = -1; d0 <= 1; ++d0) {
+    const int s0 = d0 * TS - left;                 // neighbour's padded origin, local coords
+    const int lo0 = max(0, s0), hi0 = min(TS, s0 + pe);
+    if (lo0 >= hi0) continue;
+    const int t0 = (tc0 + d0) & (w.nts[0] - 1);
+    for (int d1 = -1; d1 <= 1; ++d1) {
+      const int s1 = d1 * TS - left;
+      if (max(0, s1) >= min(TS, s1 + pe)) continue;
+      const int t1 = (tc1 + d1) & (w.nts[1] - 1);
+      for (int d2 = -1; d2 <= 1; ++d2) {
+        const int s2 = d2 * TS - left;
+        if (max(0, s2) >= min(TS, s2 + pe)) continue;
+        const int t2 = (tc2 + d2) & (w.nts[2] - 1);
+        const int gt = w.tile_off + (((t0 << w.lnts[1]) + t1) << w.lnts[2]) + t2;
+        const int ns = tile_nslot[gt];
+        if (ns == 0) continue;
+        const int p1 = x1 - s1, p2 = x2 - s2;        // padded indices of this column
+        if (p1 < 0 || p1 >= pe || p2 < 0 || p2 >= pe) continue;
+        const T* src = padded + (long long)tile_slot0[gt] * slot_stride + p1 * pe2 + p2;
+#pragma unroll
+        for (int x0 = 0; x0 < TS; ++x0) {
+          if (x0 < lo0 || x0 >= hi0) continue;
+          const T* q = src + (long long)(x0 - s0) * pe12;
+          T sum = (T)0;
+          for (int k = 0; k < ns; ++k) sum += q[(long long)k * slot_stride];
+          acc[x0] += sum;
+        }
+      }
+    }
+  }
+  T* g = grid + w.grid_off;
+  const int o0 = tc0 * TS, o1 = tc1 * TS, o2 = tc2 * TS;
+#pragma unroll
+  for (int x0 = 0; x0 < TS; ++x0)
+    g[((long long)(o0 + x0) * w.n[1] + (o1 + x1)) * w.n[2] + (o2 + x2)] = acc[x0];
 }
 
 // ---------------------------------------------------------------------------- convolution
@@ -327,64 +477,63 @@ k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     }
     __syncthreads();
   }
-  const T b = (T)w.b, den = (T)w.kb_den;
+  // window polynomials: from global (scalar loads) when small, else staged in LDS
+  constexpr int KP = PsiDeg<T>::value + 1;
+  constexpr bool PSI_LDS = (W * KP * (int)sizeof(T) / 4) > 96;
+  __shared__ T s_psi[PSI_LDS ? W * KP : 1];
+  const T* psi = reinterpret_cast<const T*>(w.psi);
+  if constexpr (PSI_LDS) {
+    for (int c = threadIdx.x; c < W * KP; c += kGatherThreads) s_psi[c] = psi[c];
+    __syncthreads();
+    psi = s_psi;
+  }
   const long long ybase = (long long)job.win * N;
+  constexpr int K = KP;
+  // large rows (FP64, m >= 6): evaluate the middle dimension's weights inside the loop instead of
+  // keeping a second register row, to stay within the register file
+  constexpr bool BIG = W * (int)sizeof(T) > 64;
   for (int p = job.pbeg + threadIdx.x; p < job.pend; p += kGatherThreads) {
     const unsigned bb = g_base[p];
     const int b2 = (int)((bb >> 16) & 255u), b1 = (int)((bb >> 8) & 255u), b0 = (int)(bb & 255u);
     T w2[W];
-    tap_row<T, W>(g_frac[2 * LN + p], b, den, w2);
-    T w1[W];
-    if constexpr (TD >= 2) tap_row<T, W>(g_frac[LN + p], b, den, w1);
+    poly_row<T, W>(psi, g_frac[2 * LN + p], w2);
+    const T x1 = (TD >= 2) ? (T)2 * g_frac[LN + p] - (T)1 : (T)0;
+    T w1[BIG ? 1 : W];
+    if constexpr (TD >= 2 && !BIG) poly_row<T, W>(psi, g_frac[LN + p], w1);
+    const T x0 = (TD == 3) ? (T)2 * g_frac[p] - (T)1 : (T)0;
+    int c2[W];
+#pragma unroll
+    for (int i2 = 0; i2 < W; ++i2) c2[i2] = staged ? b2 - o2 + i2 : wrap(b2 - m + 1 + i2, n2);
+    // row start of (i0, i1) in the staged tile or in the grid
+    auto row_of = [&](int i0, int i1) -> const T* {
+      if (staged) return tile + ((b0 - o0 + i0) * pe1 + (b1 - o1 + i1)) * pe2;
+      const int g0 = (TD == 3) ? wrap(b0 - m + 1 + i0, n0) : 0;
+      const int g1 = (TD >= 2) ? wrap(b1 - m + 1 + i1, n1) : 0;
+      return h + ((long long)g0 * n1 + g1) * n2;
+    };
+    auto line = [&](const T* row) {
+      T sacc = (T)0;
+#pragma unroll
+      for (int i2 = 0; i2 < W; ++i2) sacc += row[c2[i2]] * w2[i2];
+      return sacc;
+    };
+    auto plane = [&](int i0) {
+      T pacc = (T)0;
+      if constexpr (TD == 1) {
+        pacc = line(row_of(0, 0));
+      } else if constexpr (BIG) {
+        for (int i1 = 0; i1 < W; ++i1) pacc += horner<T, K>(psi + i1 * K, x1) * line(row_of(i0, i1));
+      } else {
+#pragma unroll
+        for (int i1 = 0; i1 < W; ++i1) pacc += w1[i1] * line(row_of(i0, i1));
+      }
+      return pacc;
+    };
     T acc = (T)0;
-    if (staged) {
-      const int l2 = b2 - o2, l1 = b1 - o1, l0 = b0 - o0;
-      auto line = [&](const T* row) {
-        T sacc = (T)0;
-#pragma unroll
-        for (int i2 = 0; i2 < W; ++i2) sacc += row[i2] * w2[i2];
-        return sacc;
-      };
-      if constexpr (TD == 1) {
-        acc = line(tile + l2);
-      } else if constexpr (TD == 2) {
-#pragma unroll
-        for (int i1 = 0; i1 < W; ++i1) acc += w1[i1] * line(tile + (l1 + i1) * pe2 + l2);
-      } else {
-        const T fr0 = g_frac[p];
-        for (int i0 = 0; i0 < W; ++i0) {
-          const T* plane = tile + ((l0 + i0) * pe1 + l1) * pe2 + l2;
-          T pacc = (T)0;
-#pragma unroll
-          for (int i1 = 0; i1 < W; ++i1) pacc += w1[i1] * line(plane + i1 * pe2);
-          acc += kb_psi(fr0 + (T)(m - 1 - i0), (T)m, b, den) * pacc;
-        }
-      }
+    if constexpr (TD == 3) {
+      for (int i0 = 0; i0 < W; ++i0) acc += horner<T, K>(psi + i0 * K, x0) * plane(i0);
     } else {
-      int c2[W];
-#pragma unroll
-      for (int i2 = 0; i2 < W; ++i2) c2[i2] = wrap(b2 - m + 1 + i2, n2);
-      auto line = [&](const T* row) {
-        T sacc = (T)0;
-#pragma unroll
-        for (int i2 = 0; i2 < W; ++i2) sacc += row[c2[i2]] * w2[i2];
-        return sacc;
-      };
-      if constexpr (TD == 1) {
-        acc = line(h);
-      } else if constexpr (TD == 2) {
-#pragma unroll
-        for (int i1 = 0; i1 < W; ++i1) acc += w1[i1] * line(h + (long long)wrap(b1 - m + 1 + i1, n1) * n2);
-      } else {
-        const T fr0 = g_frac[p];
-        for (int i0 = 0; i0 < W; ++i0) {
-          const T* plane = h + (long long)wrap(b0 - m + 1 + i0, n0) * n1 * n2;
-          T pacc = (T)0;
-#pragma unroll
-          for (int i1 = 0; i1 < W; ++i1) pacc += w1[i1] * line(plane + (long long)wrap(b1 - m + 1 + i1, n1) * n2);
-          acc += kb_psi(fr0 + (T)(m - 1 - i0), (T)m, b, den) * pacc;
-        }
-      }
+      acc = plane(0);
     }
     ylocal[ybase + g_idx[p]] = acc;
   }
@@ -551,6 +700,17 @@ void matvec_t(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hi
     NLD_HIP(hipGetLastError());
   }
   tiles_dispatch<T>(P, v, st, s, false);
+  if (P.n_f3jobs > 0) {
+    if (P.f3_ts == 16)
+      hipLaunchKernelGGL((k_fold3<T, 16>), dim3(P.n_f3jobs), dim3(256), 0, s, P.d_wins, P.d_f3jobs,
+                         (const T*)P.padded, P.slot_stride, P.tile_slot0, P.tile_nslot, (T*)P.grid, st);
+    else if (P.f3_ts == 8)
+      hipLaunchKernelGGL((k_fold3<T, 8>), dim3(P.n_f3jobs), dim3(64), 0, s, P.d_wins, P.d_f3jobs,
+                         (const T*)P.padded, P.slot_stride, P.tile_slot0, P.tile_nslot, (T*)P.grid, st);
+    else
+      throw std::runtime_error("internal: unsupported 3-D tile size");
+    NLD_HIP(hipGetLastError());
+  }
   if (P.n_fjobs > 0) {
     hipLaunchKernelGGL(k_fold<T>, dim3(P.n_fjobs), dim3(256), 0, s, P.d_wins, P.d_fjobs,
                        (const T*)P.padded, P.slot_stride, P.tile_slot0, P.tile_nslot, (T*)P.grid, st);

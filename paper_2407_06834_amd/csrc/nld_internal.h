@@ -40,19 +40,29 @@ struct WinDev {
   double weight;       // w_l
   int ts[3], nts[3];   // tiles: extent and count per dimension
   int pe[3];           // padded tile extent: ts + taps - 1
+  int lts[3], lnts[3]; // log2 of ts and nts (all powers of two)
   int tile_off;        // first global tile id of this window
   long long grid_off;  // offset of this window's grid in the concatenated grid buffer
   long long grid_size; // n0 n1 n2
   const void* coef;    // [3][n_max] per-dimension Fourier multipliers (precision T)
   int n_max;
+  const void* psi;     // [2m][deg + 1] window polynomial per tap (precision T), see psi_deg
 };
+
+// Degree of the per-tap polynomial that replaces the window evaluation: the scaled
+// Kaiser-Bessel window is an entire function of the distance, so a Chebyshev interpolant on each
+// unit interval converges fast (max error ~6e-9 at degree 8 and ~3e-15 at degree 14 for m = 4..8).
+template <typename T> struct PsiDeg { static constexpr int value = sizeof(T) == 4 ? 8 : 14; };
 
 struct TileJob {       // a chunk of the nodes of one tile (spreading and gathering)
   int win, tile, pbeg, pend, slot;   // pbeg/pend: positions in the sorted node list
 };
-struct FoldJob {       // a range of grid cells of one window
+struct FoldJob {       // 256 consecutive cells of one window's grid
   int win, ncell;
   long long cell0;
+};
+struct Fold3Job {      // one tile of a 3-D window
+  int win, tile;
 };
 struct ConvJob {
   int win;
@@ -104,6 +114,8 @@ struct Plan {
   unsigned* g_base = nullptr;      // packed base cell and fractional offsets [3][L N]
   void* g_frac = nullptr;
   void* coef = nullptr;            // all windows' multipliers
+  void* psi = nullptr;             // all windows' window polynomials
+  double psi_err = 0.0;            // max abs error of the window polynomial (plan time check)
   void* grid = nullptr;            // concatenated grids
   long long grid_total = 0;
   void* padded = nullptr;          // padded tile accumulators, one slot per spreading job
@@ -122,7 +134,10 @@ struct Plan {
   TileJob* d_tjobs = nullptr;
   int tjob_begin[4] = {0, 0, 0, 0};  // jobs of group g are [tjob_begin[g], tjob_begin[g + 1])
   int max_padded = 1;              // largest padded tile (cells)
-  FoldJob* d_fjobs = nullptr; int n_fjobs = 0;
+  int max_tile_cells = 1;          // largest tile (cells)
+  FoldJob* d_fjobs = nullptr; int n_fjobs = 0;     // per-cell fold (windows with t <= 2)
+  Fold3Job* d_f3jobs = nullptr; int n_f3jobs = 0;   // per-tile fold (windows with t = 3)
+  int f3_ts = 0;                                   // tile extent of the 3-D windows (8 or 16)
   ConvJob* d_conv[3] = {nullptr, nullptr, nullptr}; int n_conv[3] = {0, 0, 0};
   int conv_lines[3] = {0, 0, 0};   // lines per conv workgroup for each axis pass
   // CG work vectors (precision T) and FP64 scratch

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <stdexcept>
@@ -17,6 +18,7 @@ namespace nld {
 namespace {
 
 constexpr int kTileChunk = 2048;     // nodes per spreading / gathering workgroup
+constexpr int kCellBits = 12;        // sort key = global tile << 12 | cell within the tile
 
 template <typename T>
 __global__ void k_features(const T* __restrict__ img, int n1, int n2, int rho, int with_pos,
@@ -115,19 +117,22 @@ __global__ void k_coords(const T* __restrict__ F, long long N, int L,
     }
     base[idx] = (unsigned)b[0] | ((unsigned)b[1] << 8) | ((unsigned)b[2] << 16);
     const int g = ((b[0] / p.ts[0]) * p.nts[1] + b[1] / p.ts[1]) * p.nts[2] + b[2] / p.ts[2];
-    key[idx] = p.tile_off + (unsigned)g;
+    const int lc = ((b[0] % p.ts[0]) * p.ts[1] + b[1] % p.ts[1]) * p.ts[2] + b[2] % p.ts[2];
+    key[idx] = ((p.tile_off + (unsigned)g) << kCellBits) | (unsigned)lc;
   }
 }
 
-// First position of every key in the sorted key array (lower bound), for keys 0..nkeys.
-__global__ void k_key_offsets(const unsigned* __restrict__ keys, long long n, int nkeys,
+// First position of every tile in the sorted key array (lower bound of tile << kCellBits),
+// for tiles 0..ntiles.
+__global__ void k_key_offsets(const unsigned* __restrict__ keys, long long n, int ntiles,
                               unsigned* __restrict__ off) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k > nkeys) return;
+  if (k > ntiles) return;
+  const unsigned long long target = (unsigned long long)k << kCellBits;
   long long lo = 0, hi = n;
   while (lo < hi) {
     const long long mid = (lo + hi) >> 1;
-    if (keys[mid] < (unsigned)k) lo = mid + 1;
+    if ((unsigned long long)keys[mid] < target) lo = mid + 1;
     else hi = mid;
   }
   off[k] = (unsigned)lo;
@@ -326,6 +331,61 @@ double kb_fourier(double k, int n, int m, double b) {
   return M_PI * m * std::cyl_bessel_i(0.0, x) / std::sinh(b * m);
 }
 
+// Scaled Kaiser-Bessel window psi(delta) = m sinh(b z) / (z sinh(b m)), z = sqrt(m^2 - delta^2).
+double kb_psi_host(double delta, int m, double b) {
+  const double z = std::sqrt(std::max(m * (double)m - delta * delta, 0.0));
+  const double den = -std::expm1(-2.0 * b * m);
+  if (z > 0.0) return (m / z) * std::exp(b * (z - m)) * (-std::expm1(-2.0 * b * z)) / den;
+  return 2.0 * b * m * std::exp(-b * m) / den;
+}
+
+// Per-tap polynomial in x = 2 fr - 1 (fr in [0, 1)) for tap i at distance fr + m - 1 - i:
+// Chebyshev interpolation at deg + 1 nodes, converted to monomial coefficients.
+// Returns the coefficients [2m][deg + 1] and the max abs error on a fine test grid.
+std::vector<double> fit_window(int m, double b, int deg, double* max_err) {
+  const int W = 2 * m, K = deg + 1;
+  std::vector<double> out((size_t)W * K, 0.0);
+  double err = 0.0;
+  for (int i = 0; i < W; ++i) {
+    std::vector<double> y(K), c(K, 0.0);
+    for (int j = 0; j < K; ++j) {
+      const double x = std::cos(M_PI * (j + 0.5) / K);
+      y[j] = kb_psi_host(0.5 * (x + 1.0) + m - 1 - i, m, b);
+    }
+    for (int k = 0; k < K; ++k) {
+      double acc = 0.0;
+      for (int j = 0; j < K; ++j) acc += y[j] * std::cos(M_PI * k * (j + 0.5) / K);
+      c[k] = acc * 2.0 / K;
+    }
+    c[0] *= 0.5;
+    std::vector<double> tprev(K, 0.0), tcur(K, 0.0), mono(K, 0.0);
+    tprev[0] = 1.0;                       // T_0
+    if (K > 1) tcur[1] = 1.0;             // T_1
+    for (int q = 0; q < K; ++q) mono[q] += c[0] * tprev[q];
+    if (K > 1)
+      for (int q = 0; q < K; ++q) mono[q] += c[1] * tcur[q];
+    for (int k = 2; k < K; ++k) {
+      std::vector<double> tn(K, 0.0);
+      for (int q = 0; q < K; ++q) {
+        if (q > 0) tn[q] += 2.0 * tcur[q - 1];
+        tn[q] -= tprev[q];
+      }
+      for (int q = 0; q < K; ++q) mono[q] += c[k] * tn[q];
+      tprev = tcur;
+      tcur = tn;
+    }
+    for (int q = 0; q < K; ++q) out[(size_t)i * K + q] = mono[q];
+    for (int s = 0; s <= 256; ++s) {
+      const double fr = s / 256.0, x = 2.0 * fr - 1.0;
+      double v = 0.0;
+      for (int q = K - 1; q >= 0; --q) v = v * x + mono[q];
+      err = std::max(err, std::abs(v - kb_psi_host(fr + m - 1 - i, m, b)));
+    }
+  }
+  *max_err = err;
+  return out;
+}
+
 int next_pow2(int v) {
   int p = 1;
   while (p < v) p <<= 1;
@@ -483,9 +543,12 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     int tsz;
     if (t == 3) {
       // the spreading accumulates the padded tile in FP64
-      tsz = 16;
+      // 8^3 tiles: smaller padded tiles in LDS give more resident workgroups, which measured
+      // faster than 16^3 tiles on the 512^2 workload despite the larger halo overhead
+      tsz = 8;
       if (const char* e = std::getenv("NLD_TILE3")) tsz = std::atoi(e);
-      while (tsz > 8 && (long long)std::pow(tsz + 2 * m - 1, 3) * 8LL > P.lds_limit) tsz /= 2;
+      if (tsz != 8 && tsz != 16) tsz = 8;
+      if ((long long)std::pow(tsz + 2 * m - 1, 3) * 8LL > P.lds_limit) tsz = 8;
     } else if (t == 2) {
       tsz = std::min(64, n);
     } else {
@@ -498,10 +561,18 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
       w.ts[dd] = p.ts[dd] = ts;
       w.nts[dd] = p.nts[dd] = w.n[dd] / ts;
       w.pe[dd] = ts + w.taps[dd] - 1;
+      w.lts[dd] = 0;
+      while ((1 << w.lts[dd]) < ts) ++w.lts[dd];
+      w.lnts[dd] = 0;
+      while ((1 << w.lnts[dd]) < w.nts[dd]) ++w.lnts[dd];
+      if ((1 << w.lts[dd]) != ts || (1 << w.lnts[dd]) != w.nts[dd])
+        throw std::invalid_argument("tile sizes must be powers of two");
       padded *= w.pe[dd];
     }
     if (padded * 8LL > P.lds_limit)
       throw std::invalid_argument("padded tile does not fit in LDS");
+    if ((long long)w.ts[0] * w.ts[1] * w.ts[2] > (1LL << kCellBits))
+      throw std::invalid_argument("tile too large for the sort key");
     max_padded = std::max<long long>(max_padded, padded);
     p.tile_off = tile_total;
     w.tile_off = (int)tile_total;
@@ -526,6 +597,23 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     P.wins[l].coef = (const T*)P.coef + (long long)l * 3 * n_max;
     P.wins[l].n_max = n_max;
   }
+  // window polynomials (same cutoff for every window; the shape b depends on M / n)
+  std::vector<T> psi_all;   // host staging buffers live until the final synchronisation
+  {
+    const int deg = PsiDeg<T>::value;
+    const int W = 2 * P.wins[0].m;
+    psi_all.assign((size_t)L * W * (deg + 1), (T)0);
+    P.psi_err = 0.0;
+    for (int l = 0; l < L; ++l) {
+      double err = 0.0;
+      const std::vector<double> c = fit_window(P.wins[l].m, P.wins[l].b, deg, &err);
+      P.psi_err = std::max(P.psi_err, err);
+      for (size_t q = 0; q < c.size(); ++q) psi_all[(size_t)l * W * (deg + 1) + q] = (T)c[q];
+    }
+    P.psi = dalloc<T>((long long)psi_all.size(), s);
+    NLD_HIP(hipMemcpyAsync(P.psi, psi_all.data(), psi_all.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    for (int l = 0; l < L; ++l) P.wins[l].psi = (const T*)P.psi + (size_t)l * W * (deg + 1);
+  }
 
   // ---- 3. coordinates of every (window, node)
   const long long LN = N * L;
@@ -544,7 +632,8 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   NLD_HIP(hipGetLastError());
   int kbits = 1;
   while ((1u << kbits) < tile_total) ++kbits;
-  radix_sort_pairs(key, val, LN, kbits, s);
+  if (kbits + kCellBits > 32) throw std::invalid_argument("too many tiles");
+  radix_sort_pairs(key, val, LN, kbits + kCellBits, s);
   P.g_idx = dalloc<int>(LN, s);
   P.g_base = dalloc<unsigned>(LN, s);
   P.g_frac = dalloc<T>(3 * LN, s);
@@ -585,6 +674,23 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     }
   }
   P.tjob_begin[3] = (int)jobs.size();
+  // largest chunks first within each group, so the long workgroups start early
+  for (int g = 0; g < 3; ++g)
+    std::stable_sort(jobs.begin() + P.tjob_begin[g], jobs.begin() + P.tjob_begin[g + 1],
+                     [](const TileJob& a, const TileJob& b) {
+                       return (a.pend - a.pbeg) > (b.pend - b.pbeg);
+                     });
+  if (std::getenv("NLD_PLAN_STATS")) {
+    long long ne = 0, maxc = 0;
+    for (unsigned gt = 0; gt < tile_total; ++gt) {
+      const long long c = (long long)ht[gt + 1] - ht[gt];
+      ne += (c > 0);
+      maxc = std::max(maxc, c);
+    }
+    std::fprintf(stderr, "plan: N=%lld L=%d tiles=%u nonempty=%lld jobs=%zu slots=%d max_tile_nodes=%lld "
+                 "max_padded=%lld psi_err=%.2e\n", (long long)N, L, tile_total, ne, jobs.size(), slots,
+                 maxc, max_padded, P.psi_err);
+  }
   P.d_tjobs = dalloc<TileJob>(std::max<size_t>(1, jobs.size()), s);
   NLD_HIP(hipMemcpyAsync(P.d_tjobs, jobs.data(), jobs.size() * sizeof(TileJob), hipMemcpyHostToDevice, s));
   P.n_tiles_total = (int)tile_total;
@@ -595,20 +701,36 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   P.max_padded = (int)max_padded;
   P.slot_stride = max_padded;
   P.padded = dalloc<T>((long long)std::max(1, slots) * max_padded, s);
-  // fold jobs: 256 grid cells each
+  // fold jobs: per tile for 3-D windows (uniform tile size), 256 grid cells each otherwise
   std::vector<FoldJob> fj;
-  for (int l = 0; l < L; ++l)
-    for (long long c = 0; P.wins[l].t > 0 && c < P.wins[l].grid_size; c += 256)
-      fj.push_back(FoldJob{l, (int)std::min<long long>(256, P.wins[l].grid_size - c), c});
+  std::vector<Fold3Job> f3;
+  P.f3_ts = 0;
+  for (int l = 0; l < L; ++l) {
+    const WinDev& w = P.wins[l];
+    if (w.t == 3) {
+      if (P.f3_ts != 0 && P.f3_ts != w.ts[0]) throw std::runtime_error("internal: mixed 3-D tile sizes");
+      if (w.ts[0] != w.ts[1] || w.ts[1] != w.ts[2]) throw std::runtime_error("internal: non-cubic tile");
+      P.f3_ts = w.ts[0];
+      const int nt = w.nts[0] * w.nts[1] * w.nts[2];
+      for (int tl = 0; tl < nt; ++tl) f3.push_back(Fold3Job{l, tl});
+    } else if (w.t > 0) {
+      for (long long c = 0; c < w.grid_size; c += 256)
+        fj.push_back(FoldJob{l, (int)std::min<long long>(256, w.grid_size - c), c});
+    }
+  }
   P.n_fjobs = (int)fj.size();
   P.d_fjobs = dalloc<FoldJob>(std::max<size_t>(1, fj.size()), s);
   NLD_HIP(hipMemcpyAsync(P.d_fjobs, fj.data(), fj.size() * sizeof(FoldJob), hipMemcpyHostToDevice, s));
+  P.n_f3jobs = (int)f3.size();
+  P.d_f3jobs = dalloc<Fold3Job>(std::max<size_t>(1, f3.size()), s);
+  NLD_HIP(hipMemcpyAsync(P.d_f3jobs, f3.data(), f3.size() * sizeof(Fold3Job), hipMemcpyHostToDevice, s));
 
   // convolution jobs: for each axis, lines of every window that has that axis; 16 lines per
   // workgroup (8 for the largest FP64 grids, to keep the LDS footprint near 32 KB)
   const int kConvLines = (n_max * (int)sizeof(T) >= 2048) ? 8 : 16;
+  std::vector<ConvJob> cjobs_all[3];
   for (int ax = 0; ax < 3; ++ax) {
-    std::vector<ConvJob> cjobs;
+    std::vector<ConvJob>& cjobs = cjobs_all[ax];
     for (int l = 0; l < L; ++l) {
       const WinDev& w = P.wins[l];
       if (w.n[ax] == 1) continue;
@@ -679,7 +801,7 @@ void build_plan(Plan& P, const void* features, hipStream_t s) {
 void release_plan(Plan& P) {
   hipStream_t s = P.stream;
   void* bufs[] = {P.d_wins, P.g_idx, P.g_base, P.g_frac, P.coef, P.grid, P.padded, P.tile_slot0,
-                  P.tile_nslot, P.ylocal, P.D, P.sumv, P.ones, P.d_tjobs, P.d_fjobs, P.d_conv[0], P.d_conv[1],
+                  P.tile_nslot, P.ylocal, P.D, P.sumv, P.ones, P.psi, P.d_tjobs, P.d_fjobs, P.d_f3jobs, P.d_conv[0], P.d_conv[1],
                   P.d_conv[2], P.z, P.r, P.p, P.q, P.red, P.st};
   for (void* b : bufs) dfree(b, s);
   (void)hipStreamSynchronize(s);
