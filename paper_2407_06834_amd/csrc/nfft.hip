@@ -349,95 +349,174 @@ k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs,
 }
 
 // ---------------------------------------------------------------------------- convolution
+// Per dimension, every grid line is circularly convolved with the window's real even kernel
+// (multiplication of its DFT by the Fourier multiplier).  Two real lines are packed as one
+// complex line.  A complex line of length N = A * B is held by B threads with A values each and
+// transformed with the four-step method: length-A DFTs in registers, twiddles, an LDS
+// exchange, length-B DFTs in registers; the multiplier is applied in that (transposed) order
+// and the inverse runs the same steps backwards, so a line visits LDS twice per transform pair.
 template <typename T>
 struct Cx {
   T x, y;
 };
-
 template <typename T>
-__device__ __forceinline__ void fft_lines(Cx<T>* a, Cx<T>* b, const Cx<T>* tw, int nlines, int n,
-                                          bool inverse, Cx<T>** out) {
-  // radix-2 Stockham autosort; tw[q] = exp(-2 pi i q / n), q < n/2
-  const int half = n >> 1;
-  const int total = nlines * half;
-  for (int p = 1; p < n; p <<= 1) {
-    const int stride = n / (2 * p);
-    for (int idx = threadIdx.x; idx < total; idx += kConvThreads) {
-      const int ln = idx / half, i = idx - ln * half;
-      const Cx<T>* x = a + ln * n;
-      Cx<T>* y = b + ln * n;
-      const int k = i & (p - 1);
-      const Cx<T> u0 = x[i];
-      const Cx<T> v1 = x[i + half];
-      Cx<T> t = tw[k * stride];
-      if (inverse) t.y = -t.y;
-      const Cx<T> u1 = {v1.x * t.x - v1.y * t.y, v1.x * t.y + v1.y * t.x};
-      const int j = (i << 1) - k;
-      y[j] = {u0.x + u1.x, u0.y + u1.y};
-      y[j + p] = {u0.x - u1.x, u0.y - u1.y};
-    }
-    __syncthreads();
-    Cx<T>* tmp = a;
-    a = b;
-    b = tmp;
-  }
-  *out = a;
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, Cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cmulc(Cx<T> a, Cx<T> b) {   // a * conj(b)
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kConvThreads)
-k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int axis, int lb,
+__host__ __device__ constexpr int bit_reverse(int i, int bits) {
+  int r = 0;
+  for (int k = 0; k < bits; ++k) r |= ((i >> k) & 1) << (bits - 1 - k);
+  return r;
+}
+__host__ __device__ constexpr int ilog2c(int p) { return p <= 1 ? 0 : 1 + ilog2c(p / 2); }
+
+// cos and sin of 2 pi q / 16, q = 0..7
+__device__ __constant__ const double kCos16[8] = {1.0, 0.92387953251128674, 0.70710678118654752,
+                                                  0.38268343236508977, 0.0, -0.38268343236508977,
+                                                  -0.70710678118654752, -0.92387953251128674};
+__device__ __constant__ const double kSin16[8] = {0.0, 0.38268343236508977, 0.70710678118654752,
+                                                  0.92387953251128674, 1.0, 0.92387953251128674,
+                                                  0.70710678118654752, 0.38268343236508977};
+
+// In-register DFT of length P (power of two, P <= 16), natural order in and out; forward uses
+// exp(-2 pi i jk / P), inverse exp(+2 pi i jk / P), no normalisation.
+template <typename T, int P, bool INV>
+__device__ __forceinline__ void dft_reg(Cx<T>* v) {
+  constexpr int LB = ilog2c(P);
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const int r = bit_reverse(i, LB);
+    if (r > i) {
+      const Cx<T> t = v[i];
+      v[i] = v[r];
+      v[r] = t;
+    }
+  }
+#pragma unroll
+  for (int len = 2; len <= P; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < P; i += len) {
+#pragma unroll
+      for (int k = 0; k < len / 2; ++k) {
+        const int q = k * (16 / len);
+        const Cx<T> wv = {(T)kCos16[q], INV ? (T)kSin16[q] : -(T)kSin16[q]};
+        const Cx<T> a = v[i + k];
+        const Cx<T> bb = cmul(v[i + k + len / 2], wv);
+        v[i + k] = {a.x + bb.x, a.y + bb.y};
+        v[i + k + len / 2] = {a.x - bb.x, a.y - bb.y};
+      }
+    }
+  }
+}
+
+template <int N> struct FftShape {
+  static constexpr int A = (N >= 128) ? 16 : 8;   // values per thread
+  static constexpr int B = N / A;                 // threads per complex line
+  static constexpr int CL = (256 / B < N / 2) ? 256 / B : N / 2;   // complex lines per workgroup
+  static constexpr int RL = 2 * CL;               // real lines per workgroup
+  static constexpr int SP = N + 1;                // padded LDS line stride (elements)
+};
+
+template <typename T, int N>
+__global__ void __launch_bounds__(256)
+k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int job0, int axis,
        T* __restrict__ grid, const CgState* __restrict__ st) {
   if (st && st->done) return;
+  using S = FftShape<N>;
+  constexpr int A = S::A, B = S::B, CL = S::CL, RL = S::RL, SP = S::SP;
   extern __shared__ unsigned char smem_raw[];
-  const ConvJob job = jobs[blockIdx.x];
+  T* stage = reinterpret_cast<T*>(smem_raw);                      // RL * SP reals
+  Cx<T>* ex = reinterpret_cast<Cx<T>*>(smem_raw);                 // CL * SP complex (same bytes)
+  Cx<T>* tw = reinterpret_cast<Cx<T>*>(smem_raw + (size_t)RL * SP * sizeof(T));  // N twiddles
+  const ConvJob job = jobs[job0 + blockIdx.x];
   const WinDev& w = wins[job.win];
-  const int n = w.n[axis];
-  const int nc = lb / 2;                        // complex lines
-  Cx<T>* buf0 = reinterpret_cast<Cx<T>*>(smem_raw);
-  Cx<T>* buf1 = buf0 + nc * w.n_max;
-  Cx<T>* tw = buf1 + nc * w.n_max;
-  for (int q = threadIdx.x; q < n / 2; q += kConvThreads) {
+  for (int q = threadIdx.x; q < N; q += 256) {
     T sn, cs;
-    if constexpr (sizeof(T) == 4) sincospif(-2.0f * (float)q / (float)n, &sn, &cs);
-    else sincospi(-2.0 * (double)q / (double)n, &sn, &cs);
+    if constexpr (sizeof(T) == 4) sincospif(-2.0f * (float)q / (float)N, &sn, &cs);
+    else sincospi(-2.0 * (double)q / (double)N, &sn, &cs);
     tw[q] = {cs, sn};
   }
-  long long es, ls;   // element stride along the line, stride between adjacent lines
-  if (axis == 2) { es = 1; ls = n; }
+  long long es, ls;   // element stride along a line, stride between adjacent lines
+  if (axis == 2) { es = 1; ls = N; }
   else if (axis == 1) { es = w.n[2]; ls = 1; }
   else { es = (long long)w.n[1] * w.n[2]; ls = 1; }
   T* g = grid + w.grid_off + job.off;
-  const int total = lb * n;
-  for (int idx = threadIdx.x; idx < total; idx += kConvThreads) {
+  const int nl = job.nl;
+  for (int idx = threadIdx.x; idx < RL * N; idx += 256) {
     int ln, c;
-    if (axis == 2) { ln = idx / n; c = idx - ln * n; }
-    else { c = idx / lb; ln = idx - c * lb; }
-    const T val = (ln < job.nl) ? g[c * es + ln * ls] : (T)0;
-    T* slot = reinterpret_cast<T*>(&buf0[(ln >> 1) * n + c]);
-    slot[ln & 1] = val;
+    if (axis == 2) { ln = idx / N; c = idx - ln * N; }
+    else { c = idx / RL; ln = idx - c * RL; }
+    stage[ln * SP + c] = (ln < nl) ? g[c * es + ln * ls] : (T)0;
   }
   __syncthreads();
-  Cx<T>* res;
-  fft_lines<T>(buf0, buf1, tw, nc, n, false, &res);
+  const int ql = threadIdx.x / B, j1 = threadIdx.x % B;
+  const bool act = ql < CL;
   const T* coef = reinterpret_cast<const T*>(w.coef) + (long long)axis * w.n_max;
-  for (int idx = threadIdx.x; idx < nc * n; idx += kConvThreads) {
-    const int k = idx % n;
-    const T c = coef[k];
-    res[idx].x *= c;
-    res[idx].y *= c;
+  Cx<T> v[A];
+  if (act) {
+#pragma unroll
+    for (int j2 = 0; j2 < A; ++j2) {
+      const int c = j1 + B * j2;
+      v[j2] = {stage[(2 * ql) * SP + c], stage[(2 * ql + 1) * SP + c]};
+    }
+    dft_reg<T, A, false>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < A; ++k2) v[k2] = cmul(v[k2], tw[(j1 * k2) & (N - 1)]);
   }
   __syncthreads();
-  Cx<T>* other = (res == buf0) ? buf1 : buf0;
-  fft_lines<T>(res, other, tw, nc, n, true, &res);
-  for (int idx = threadIdx.x; idx < total; idx += kConvThreads) {
-    int ln, c;
-    if (axis == 2) { ln = idx / n; c = idx - ln * n; }
-    else { c = idx / lb; ln = idx - c * lb; }
-    if (ln < job.nl) {
-      const T* slot = reinterpret_cast<const T*>(&res[(ln >> 1) * n + c]);
-      g[c * es + ln * ls] = slot[ln & 1];
+  if (act) {
+#pragma unroll
+    for (int k2 = 0; k2 < A; ++k2) ex[ql * SP + k2 * B + j1] = v[k2];
+  }
+  __syncthreads();
+  constexpr int R = A / B > 0 ? A / B : 1;       // length-B DFTs per thread
+  if (act) {
+    Cx<T> u[R][B];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int k2 = j1 * R + r;
+#pragma unroll
+      for (int k1 = 0; k1 < B; ++k1) u[r][k1] = ex[ql * SP + k2 * B + k1];
+      dft_reg<T, B, false>(u[r]);                 // u[r][k1] = X[k2 + A k1]
+#pragma unroll
+      for (int k1 = 0; k1 < B; ++k1) {
+        const T cm = coef[k2 + A * k1];
+        u[r][k1].x *= cm;
+        u[r][k1].y *= cm;
+      }
+      dft_reg<T, B, true>(u[r]);                  // u[r][j1'] = Z[k2][j1']
+#pragma unroll
+      for (int j = 0; j < B; ++j) u[r][j] = cmulc(u[r][j], tw[(j * k2) & (N - 1)]);
+#pragma unroll
+      for (int j = 0; j < B; ++j) ex[ql * SP + k2 * B + j] = u[r][j];
     }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int k2 = 0; k2 < A; ++k2) v[k2] = ex[ql * SP + k2 * B + j1];
+    dft_reg<T, A, true>(v);                       // v[j2] = x'[j1 + B j2]
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int j2 = 0; j2 < A; ++j2) {
+      const int c = j1 + B * j2;
+      stage[(2 * ql) * SP + c] = v[j2].x;
+      stage[(2 * ql + 1) * SP + c] = v[j2].y;
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < RL * N; idx += 256) {
+    int ln, c;
+    if (axis == 2) { ln = idx / N; c = idx - ln * N; }
+    else { c = idx / RL; ln = idx - c * RL; }
+    if (ln < nl) g[c * es + ln * ls] = stage[ln * SP + c];
   }
 }
 
@@ -690,6 +769,17 @@ void tiles_dispatch(Plan& P, const void* v, const CgState* st, hipStream_t s, bo
   }
 }
 
+template <typename T, int N>
+void launch_conv(Plan& P, int ax, int j0, int nj, const CgState* st, hipStream_t s) {
+  using S = FftShape<N>;
+  const size_t lds = (size_t)S::RL * S::SP * sizeof(T) + (size_t)N * 2 * sizeof(T);
+  if (lds > 65536)
+    NLD_HIP(hipFuncSetAttribute((const void*)k_conv<T, N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((k_conv<T, N>), dim3(nj), dim3(256), lds, s, P.d_wins, P.d_conv[ax], j0, ax,
+                     (T*)P.grid, st);
+  NLD_HIP(hipGetLastError());
+}
+
 template <typename T>
 void matvec_t(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hipStream_t s) {
   const bool cg = (epi == EPI_CG_Q || epi == EPI_CG_INIT || epi == EPI_CG_TRUE);
@@ -716,15 +806,17 @@ void matvec_t(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hi
                        (const T*)P.padded, P.slot_stride, P.tile_slot0, P.tile_nslot, (T*)P.grid, st);
     NLD_HIP(hipGetLastError());
   }
-  int n_max = 1;
-  for (const auto& w : P.wins) n_max = std::max(n_max, w.n_max);
   for (int ax = 2; ax >= 0; --ax) {
-    if (P.n_conv[ax] == 0) continue;
-    const int lb = P.conv_lines[ax];
-    const size_t lds = (size_t)(2 * (lb / 2) * n_max + n_max / 2 + 1) * 2 * sizeof(T);
-    hipLaunchKernelGGL(k_conv<T>, dim3(P.n_conv[ax]), dim3(kConvThreads), lds, s, P.d_wins,
-                       P.d_conv[ax], ax, lb, (T*)P.grid, st);
-    NLD_HIP(hipGetLastError());
+    for (int gi = 0; gi < 4; ++gi) {
+      const int j0 = P.conv_begin[ax][gi], nj = P.conv_begin[ax][gi + 1] - j0;
+      if (nj == 0) continue;
+      switch (gi) {
+        case 0: launch_conv<T, 32>(P, ax, j0, nj, st, s); break;
+        case 1: launch_conv<T, 64>(P, ax, j0, nj, st, s); break;
+        case 2: launch_conv<T, 128>(P, ax, j0, nj, st, s); break;
+        default: launch_conv<T, 256>(P, ax, j0, nj, st, s); break;
+      }
+    }
   }
   tiles_dispatch<T>(P, v, st, s, true);
   ReduceArgs a;

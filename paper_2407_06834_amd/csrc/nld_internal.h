@@ -138,8 +138,9 @@ struct Plan {
   FoldJob* d_fjobs = nullptr; int n_fjobs = 0;     // per-cell fold (windows with t <= 2)
   Fold3Job* d_f3jobs = nullptr; int n_f3jobs = 0;   // per-tile fold (windows with t = 3)
   int f3_ts = 0;                                   // tile extent of the 3-D windows (8 or 16)
-  ConvJob* d_conv[3] = {nullptr, nullptr, nullptr}; int n_conv[3] = {0, 0, 0};
-  int conv_lines[3] = {0, 0, 0};   // lines per conv workgroup for each axis pass
+  // convolution jobs per axis, grouped by grid size n = 32, 64, 128, 256 (group g: n = 32 << g)
+  ConvJob* d_conv[3] = {nullptr, nullptr, nullptr};
+  int conv_begin[3][5] = {{0}};
   // CG work vectors (precision T) and FP64 scratch
   void* z = nullptr; void* r = nullptr; void* p = nullptr; void* q = nullptr;
   double* red = nullptr;           // reduction partials [kRedBlocks][8]

@@ -725,32 +725,36 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   P.d_f3jobs = dalloc<Fold3Job>(std::max<size_t>(1, f3.size()), s);
   NLD_HIP(hipMemcpyAsync(P.d_f3jobs, f3.data(), f3.size() * sizeof(Fold3Job), hipMemcpyHostToDevice, s));
 
-  // convolution jobs: for each axis, lines of every window that has that axis; 16 lines per
-  // workgroup (8 for the largest FP64 grids, to keep the LDS footprint near 32 KB)
-  const int kConvLines = (n_max * (int)sizeof(T) >= 2048) ? 8 : 16;
+  // convolution jobs: for each axis, lines of every window that has that axis, grouped by the
+  // grid size n; each job holds the real lines one workgroup transforms (64 for n = 64 and 128,
+  // 32 for n = 32 and 256), adjacent in memory along the contiguous dimension
   std::vector<ConvJob> cjobs_all[3];
   for (int ax = 0; ax < 3; ++ax) {
     std::vector<ConvJob>& cjobs = cjobs_all[ax];
-    for (int l = 0; l < L; ++l) {
-      const WinDev& w = P.wins[l];
-      if (w.n[ax] == 1) continue;
-      const int n0 = w.n[0], n1 = w.n[1], n2 = w.n[2];
-      if (ax == 2) {
-        const long long lines = (long long)n0 * n1;
-        for (long long q = 0; q < lines; q += kConvLines)
-          cjobs.push_back(ConvJob{l, (int)std::min<long long>(kConvLines, lines - q), q * n2});
-      } else if (ax == 1) {
-        for (int i0 = 0; i0 < n0; ++i0)
-          for (int i2 = 0; i2 < n2; i2 += kConvLines)
-            cjobs.push_back(ConvJob{l, std::min(kConvLines, n2 - i2), (long long)i0 * n1 * n2 + i2});
-      } else {
-        for (int i1 = 0; i1 < n1; ++i1)
-          for (int i2 = 0; i2 < n2; i2 += kConvLines)
-            cjobs.push_back(ConvJob{l, std::min(kConvLines, n2 - i2), (long long)i1 * n2 + i2});
+    for (int gi = 0; gi < 4; ++gi) {
+      P.conv_begin[ax][gi] = (int)cjobs.size();
+      const int ng = 32 << gi;
+      const int lines_per = (ng == 64 || ng == 128) ? 64 : 32;
+      for (int l = 0; l < L; ++l) {
+        const WinDev& w = P.wins[l];
+        if (w.n[ax] == 1 || w.n[ax] != ng) continue;
+        const int n0 = w.n[0], n1 = w.n[1], n2 = w.n[2];
+        if (ax == 2) {
+          const long long lines = (long long)n0 * n1;
+          for (long long q = 0; q < lines; q += lines_per)
+            cjobs.push_back(ConvJob{l, (int)std::min<long long>(lines_per, lines - q), q * n2});
+        } else if (ax == 1) {
+          for (int i0 = 0; i0 < n0; ++i0)
+            for (int i2 = 0; i2 < n2; i2 += lines_per)
+              cjobs.push_back(ConvJob{l, std::min(lines_per, n2 - i2), (long long)i0 * n1 * n2 + i2});
+        } else {
+          for (int i1 = 0; i1 < n1; ++i1)
+            for (int i2 = 0; i2 < n2; i2 += lines_per)
+              cjobs.push_back(ConvJob{l, std::min(lines_per, n2 - i2), (long long)i1 * n2 + i2});
+        }
       }
     }
-    P.n_conv[ax] = (int)cjobs.size();
-    P.conv_lines[ax] = kConvLines;
+    P.conv_begin[ax][4] = (int)cjobs.size();
     if (!cjobs.empty()) {
       P.d_conv[ax] = dalloc<ConvJob>(cjobs.size(), s);
       NLD_HIP(hipMemcpyAsync(P.d_conv[ax], cjobs.data(), cjobs.size() * sizeof(ConvJob),
