@@ -204,6 +204,31 @@ def fast_gauss_window(X: np.ndarray, v: np.ndarray, sigma: float, M: int, n: int
     return gather(h, u, m, b)
 
 
+def fast_sigma_derivative_window(X, v, sigma, M, n, m):
+    """Approximate sum_j v_j (2 r_ij^2 / sigma^2) exp(-r_ij^2 / sigma^2) for one window X (t, N):
+    the kernel sigma dK/dsigma.  Its Fourier coefficients follow from those of the Gaussian by
+    differentiating the Poisson-summation formula: bhat_k (t - 2 pi^2 sum_d st_d^2 k_d^2), a
+    non-separable factor, applied here on the full t-dimensional spectrum."""
+    kept, centres, scales, st = torus_scaling(X, sigma, M)
+    if not kept:                       # identical nodes: r = 0, the kernel vanishes
+        return np.zeros(X.shape[1])
+    xt = np.stack([(X[d] - c) * s for d, c, s in zip(kept, centres, scales)])
+    u = grid_coords(xt, n)
+    b = kb_shape(n, M)
+    g = spread(u, v, n, m, b)
+    t = len(kept)
+    k = fft_frequencies(n)
+    G = np.fft.fftn(g)
+    factor = np.full(G.shape, float(t))
+    for d in range(t):
+        shape = [1] * t
+        shape[d] = n
+        G = G * conv_multiplier(n, M, m, st[d]).reshape(shape)
+        factor = factor - 2.0 * math.pi ** 2 * st[d] ** 2 * (k ** 2).reshape(shape)
+    h = (np.fft.ifftn(G * factor) * n ** t).real
+    return gather(h, u, m, b)
+
+
 def anova_matvec_nfft(F, wins, sigmas, weights, v, M, n, m):
     """W~ v = sum_l w_l K~_l v with one fast Gauss summation per window (Sec. 3)."""
     y = np.zeros(F.shape[1])

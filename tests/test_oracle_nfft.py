@@ -185,3 +185,13 @@ def test_dropped_constant_dimension():
     y2 = nfft.fast_gauss_window(X, v, 0.2, 32, 64, 6)
     y3 = nfft.fast_gauss_window(X3, v, 0.2, 32, 64, 6)
     np.testing.assert_array_equal(y2, y3)
+
+
+def test_sigma_derivative_summation_against_dense():
+    from oracle.gradient import sigma_derivative_kernel
+    for t in (1, 2, 3):
+        X, v = _window_setup(t, 250, seed=20 + t)
+        F = X
+        y = nfft.fast_sigma_derivative_window(X, v, 0.15, 48, 96, 6)
+        yd = sigma_derivative_kernel(F, list(range(t)), 0.15) @ v
+        assert np.linalg.norm(y - yd) / np.linalg.norm(yd) < 1e-7
