@@ -143,6 +143,23 @@ typedef struct {
 nld_status pcg_solve(nfft_plan_t plan, double alpha, const void* f, void* u,
                      const nld_pcg_opts* opts, nld_pcg_info* info, hipStream_t s);
 
+/* Bilevel gradient by the adjoint method (paper Sec. 2.4 optimality system, Sec. 5.5):
+ * given the state u of (I + alpha L~) u = f and g = dJ/du (device, precision of the plan),
+ * solves A p = g with the same operator and options as pcg_solve (p: device, out; if
+ * opts->use_u0, p holds the initial guess on entry), then writes to grad (host, 1 + 2L doubles)
+ *   grad[0]         = dJ/dlog(alpha)   = sum_l w_l dJ/dw_l
+ *   grad[1 + l]     = dJ/dlog(sigma_l) = -alpha w_l p^T L^s_l u
+ *   grad[1 + L + l] = dJ/dw_l          = -alpha p^T L_l u
+ * where L_l is the Laplacian of window l's kernel and L^s_l that of sigma_l dK_l/dsigma_l =
+ * (2 r^2 / sigma_l^2) exp(-r^2 / sigma_l^2), both evaluated by NFFT fast summation (the
+ * derivative kernel's Fourier coefficients are the Gaussian's times t - 2 pi^2 sum_d
+ * st_d^2 k_d^2).  Features are treated as data; dJ/df is p.  f is accepted for the interface
+ * and validated but not read (the state enters through u).  Blocks; fills *info for the adjoint
+ * solve.  */
+nld_status adjoint_solve(nfft_plan_t plan, double alpha, const void* f, const void* u, const void* g,
+                         void* p, double* grad, const nld_pcg_opts* opts, nld_pcg_info* info,
+                         hipStream_t s);
+
 /* Features of an n1 x n2 image (device, row-major, element type of prec) into the SoA
  * matrix features [d][N] (device), d = 2*with_pos + (2 rho + 1)^2, N = n1 n2: position
  * (col/n2, row/n1) then the patch intensities of radius rho in raster order of the offsets,

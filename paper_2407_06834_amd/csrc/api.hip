@@ -227,4 +227,32 @@ nld_status pcg_solve(nfft_plan_t plan, double alpha, const void* f, void* u,
   return result;
 }
 
+nld_status adjoint_solve(nfft_plan_t plan, double alpha, const void* f, const void* u,
+                         const void* g, void* p, double* grad, const nld_pcg_opts* opts,
+                         nld_pcg_info* info, hipStream_t s) {
+  if (!plan || !f || !u || !g || !p || !grad || !opts || !info)
+    return fail(NLD_E_INVAL, "adjoint_solve: null pointer");
+  if (!finite_pos(alpha)) return fail(NLD_E_INVAL, "adjoint_solve: alpha must be finite and > 0");
+  if (!finite_pos(opts->tol) || opts->tol >= 1.0) return fail(NLD_E_INVAL, "adjoint_solve: tol must be in (0, 1)");
+  if (opts->maxit < 0) return fail(NLD_E_INVAL, "adjoint_solve: maxit must be >= 0");
+  if ((opts->precond != 0 && opts->precond != 1) || (opts->deflate != 0 && opts->deflate != 1) ||
+      (opts->use_u0 != 0 && opts->use_u0 != 1))
+    return fail(NLD_E_INVAL, "adjoint_solve: precond, deflate and use_u0 must be 0 or 1");
+  std::memset(info, 0, sizeof(*info));
+  info->relres_true = -1.0;
+  nld_status result = NLD_OK;
+  nld_status st = guarded("adjoint_solve", [&] {
+    plan->P.stream = s;
+    result = nld::run_adjoint(plan->P, alpha, u, g, p, grad, *opts, *info, s);
+    return NLD_OK;
+  });
+  if (st != NLD_OK) {
+    info->status = st;
+    return st;
+  }
+  if (result == NLD_E_NOCONV) nld::set_error("adjoint_solve: maximum number of iterations reached");
+  if (result == NLD_E_BREAKDOWN) nld::set_error("adjoint_solve: CG breakdown");
+  return result;
+}
+
 }  // extern "C"

@@ -770,21 +770,34 @@ void tiles_dispatch(Plan& P, const void* v, const CgState* st, hipStream_t s, bo
 }
 
 template <typename T, int N>
-void launch_conv(Plan& P, int ax, int j0, int nj, const CgState* st, hipStream_t s) {
+void launch_conv(Plan& P, const WinDev* wins, int ax, int j0, int nj, const CgState* st, hipStream_t s) {
   using S = FftShape<N>;
   const size_t lds = (size_t)S::RL * S::SP * sizeof(T) + (size_t)N * 2 * sizeof(T);
   if (lds > 65536)
     NLD_HIP(hipFuncSetAttribute((const void*)k_conv<T, N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_conv<T, N>), dim3(nj), dim3(256), lds, s, P.d_wins, P.d_conv[ax], j0, ax,
+  hipLaunchKernelGGL((k_conv<T, N>), dim3(nj), dim3(256), lds, s, wins, P.d_conv[ax], j0, ax,
                      (T*)P.grid, st);
   NLD_HIP(hipGetLastError());
 }
 
 template <typename T>
-void matvec_t(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hipStream_t s) {
-  const bool cg = (epi == EPI_CG_Q || epi == EPI_CG_INIT || epi == EPI_CG_TRUE);
-  // only the iteration's product stops early once the solve has finished
-  const CgState* st = (epi == EPI_CG_Q) ? P.st : nullptr;
+void conv_all(Plan& P, const WinDev* wins, const CgState* st, hipStream_t s) {
+  for (int ax = 2; ax >= 0; --ax) {
+    for (int gi = 0; gi < 4; ++gi) {
+      const int j0 = P.conv_begin[ax][gi], nj = P.conv_begin[ax][gi + 1] - j0;
+      if (nj == 0) continue;
+      switch (gi) {
+        case 0: launch_conv<T, 32>(P, wins, ax, j0, nj, st, s); break;
+        case 1: launch_conv<T, 64>(P, wins, ax, j0, nj, st, s); break;
+        case 2: launch_conv<T, 128>(P, wins, ax, j0, nj, st, s); break;
+        default: launch_conv<T, 256>(P, wins, ax, j0, nj, st, s); break;
+      }
+    }
+  }
+}
+
+template <typename T>
+void spread_fold(Plan& P, const void* v, const CgState* st, hipStream_t s) {
   if (P.has_flat) {
     hipLaunchKernelGGL(k_sum<T>, dim3(1), dim3(1024), 0, s, (const T*)v, (long long)P.N, P.sumv, st);
     NLD_HIP(hipGetLastError());
@@ -806,18 +819,126 @@ void matvec_t(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hi
                        (const T*)P.padded, P.slot_stride, P.tile_slot0, P.tile_nslot, (T*)P.grid, st);
     NLD_HIP(hipGetLastError());
   }
-  for (int ax = 2; ax >= 0; --ax) {
-    for (int gi = 0; gi < 4; ++gi) {
-      const int j0 = P.conv_begin[ax][gi], nj = P.conv_begin[ax][gi + 1] - j0;
-      if (nj == 0) continue;
-      switch (gi) {
-        case 0: launch_conv<T, 32>(P, ax, j0, nj, st, s); break;
-        case 1: launch_conv<T, 64>(P, ax, j0, nj, st, s); break;
-        case 2: launch_conv<T, 128>(P, ax, j0, nj, st, s); break;
-        default: launch_conv<T, 256>(P, ax, j0, nj, st, s); break;
+}
+
+// per-window results of the flat windows (no kept dimension): K = 1 1^T, sigma dK/dsigma = 0
+template <typename T>
+__global__ void k_flat_parts(const WinDev* __restrict__ wins, int L, long long N,
+                             const double* __restrict__ sumv, T* __restrict__ yk, T* __restrict__ yks) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x)
+    for (int l = 0; l < L; ++l)
+      if (wins[l].t == 0) {
+        yk[(long long)l * N + i] = (T)*sumv;
+        yks[(long long)l * N + i] = (T)0;
+      }
+}
+
+template <typename T>
+__global__ void k_axpy_windows(const T* __restrict__ src, T* __restrict__ dst, long long n, int first) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = first ? src[i] : dst[i] + src[i];
+}
+
+template <typename T>
+void matvec_parts_t(Plan& P, const void* v, void* yk, void* yks, hipStream_t s) {
+  const long long LN = (long long)P.N * P.L;
+  const size_t gbytes = (size_t)P.grid_total * sizeof(T);
+  spread_fold<T>(P, v, nullptr, s);
+  NLD_HIP(hipMemcpyAsync(P.grid_save, P.grid, gbytes, hipMemcpyDeviceToDevice, s));
+  conv_all<T>(P, P.d_wins, nullptr, s);
+  tiles_dispatch<T>(P, v, nullptr, s, true);
+  NLD_HIP(hipMemcpyAsync(yk, P.ylocal, LN * sizeof(T), hipMemcpyDeviceToDevice, s));
+  bool first = true;
+  for (int d = 0; d < 3; ++d) {
+    if (!P.dv_used[d]) continue;
+    NLD_HIP(hipMemcpyAsync(P.grid, P.grid_save, gbytes, hipMemcpyDeviceToDevice, s));
+    conv_all<T>(P, P.d_wins_dv[d], nullptr, s);
+    tiles_dispatch<T>(P, v, nullptr, s, true);
+    hipLaunchKernelGGL(k_axpy_windows<T>, dim3(grid_for(LN)), dim3(256), 0, s, (const T*)P.ylocal,
+                       (T*)yks, LN, first ? 1 : 0);
+    NLD_HIP(hipGetLastError());
+    first = false;
+  }
+  if (first) NLD_HIP(hipMemsetAsync(yks, 0, LN * sizeof(T), s));
+  if (P.has_flat) {
+    hipLaunchKernelGGL(k_flat_parts<T>, dim3(grid_for(P.N)), dim3(256), 0, s, P.d_wins, P.L,
+                       (long long)P.N, (const double*)P.sumv, (T*)yk, (T*)yks);
+    NLD_HIP(hipGetLastError());
+  }
+}
+
+// Per-block partial sums for the gradient: for each window l (NS = 4 L + 3 values)
+//   p u D_l,  p K_l u,  p u Ds_l,  p Ks_l u   and then  p,  u,  p u.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_grad_sums(const T* __restrict__ p, const T* __restrict__ u, const T* __restrict__ dl,
+            const T* __restrict__ ku, const T* __restrict__ dls, const T* __restrict__ ksu, int L,
+            long long N, double* __restrict__ part) {
+  const int NS = 4 * L + 3;
+  __shared__ double sh[256];
+  for (int k = 0; k < NS; ++k) {
+    const int l = k / 4, kind = k % 4;
+    double a = 0.0;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < N; i += (long long)gridDim.x * 256) {
+      const double pi = (double)p[i], ui = (double)u[i];
+      if (k < 4 * L) {
+        const long long o = (long long)l * N + i;
+        if (kind == 0) a += pi * ui * (double)dl[o];
+        else if (kind == 1) a += pi * (double)ku[o];
+        else if (kind == 2) a += pi * ui * (double)dls[o];
+        else a += pi * (double)ksu[o];
+      } else if (k == 4 * L) {
+        a += pi;
+      } else if (k == 4 * L + 1) {
+        a += ui;
+      } else {
+        a += pi * ui;
       }
     }
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+      if ((int)threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * NS + k] = sh[0];
+    __syncthreads();
   }
+}
+
+__global__ void k_grad_final(const double* __restrict__ part, int nblk, int NS, double* __restrict__ out) {
+  for (int k = threadIdx.x; k < NS; k += blockDim.x) {
+    double a = 0.0;
+    for (int b = 0; b < nblk; ++b) a += part[(long long)b * NS + k];
+    out[k] = a;
+  }
+}
+
+template <typename T>
+void gradient_sums_t(Plan& P, const void* p, const void* u, std::vector<double>& out, hipStream_t s) {
+  const int NS = 4 * P.L + 3;
+  const int nblk = (int)std::min<long long>(256, (P.N + 255) / 256);
+  double* part = P.adj_part;
+  hipLaunchKernelGGL(k_grad_sums<T>, dim3(nblk), dim3(256), 0, s, (const T*)p, (const T*)u,
+                     (const T*)P.dl, (const T*)P.yk, (const T*)P.dls, (const T*)P.yks, P.L,
+                     (long long)P.N, part);
+  double* fin = part + (long long)nblk * NS;
+  hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(256), 0, s, (const double*)part, nblk, NS, fin);
+  NLD_HIP(hipGetLastError());
+  out.assign(NS, 0.0);
+  NLD_HIP(hipMemcpyAsync(out.data(), fin, NS * sizeof(double), hipMemcpyDeviceToHost, s));
+  NLD_HIP(hipStreamSynchronize(s));
+}
+
+template <typename T>
+void matvec_t(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hipStream_t s) {
+  const bool cg = (epi == EPI_CG_Q || epi == EPI_CG_INIT || epi == EPI_CG_TRUE);
+  // only the iteration's product stops early once the solve has finished
+  const CgState* st = (epi == EPI_CG_Q) ? P.st : nullptr;
+  spread_fold<T>(P, v, st, s);
+  conv_all<T>(P, P.d_wins, st, s);
   tiles_dispatch<T>(P, v, st, s, true);
   ReduceArgs a;
   a.yl = P.ylocal;
@@ -839,6 +960,16 @@ void matvec_t(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hi
 }
 
 }  // namespace
+
+void matvec_parts(Plan& P, const void* v, void* yk, void* yks, hipStream_t s) {
+  if (P.prec == NLD_FP32) matvec_parts_t<float>(P, v, yk, yks, s);
+  else matvec_parts_t<double>(P, v, yk, yks, s);
+}
+
+void gradient_sums(Plan& P, const void* p, const void* u, std::vector<double>& out, hipStream_t s) {
+  if (P.prec == NLD_FP32) gradient_sums_t<float>(P, p, u, out, s);
+  else gradient_sums_t<double>(P, p, u, out, s);
+}
 
 void matvec(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hipStream_t s) {
   if (P.prec == NLD_FP32) matvec_t<float>(P, v, out, epi, f, s);

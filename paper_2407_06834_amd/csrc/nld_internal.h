@@ -115,6 +115,19 @@ struct Plan {
   void* g_frac = nullptr;
   void* coef = nullptr;            // all windows' multipliers
   void* psi = nullptr;             // all windows' window polynomials
+  // sigma-derivative kernel: for pass d, multiplier tables with dimension d's factor multiplied
+  // by (1 - 2 pi^2 st_d^2 k^2) (zero for windows without dimension d), and window descriptors
+  // pointing at them; buffers for the per-window products of the adjoint gradient
+  void* coef_dv = nullptr;
+  WinDev* d_wins_dv[3] = {nullptr, nullptr, nullptr};
+  bool dv_used[3] = {false, false, false};
+  void* grid_save = nullptr;
+  void* yk = nullptr;              // [L][N] K_l v
+  void* yks = nullptr;             // [L][N] K^s_l v
+  void* dl = nullptr;              // [L][N] K_l 1
+  void* dls = nullptr;             // [L][N] K^s_l 1
+  double* adj_part = nullptr;      // reduction partials of the gradient sums
+  std::vector<double> sig_t;       // [L][3] scaled widths per internal dimension
   double psi_err = 0.0;            // max abs error of the window polynomial (plan time check)
   void* grid = nullptr;            // concatenated grids
   long long grid_total = 0;
@@ -161,9 +174,17 @@ enum Epilogue { EPI_ANOVA = 0, EPI_LAPLACIAN = 1, EPI_DEGREE = 2, EPI_CG_Q = 3, 
 // Runs the per-window fast summations on v and the window reduction with the epilogue.
 void matvec(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hipStream_t s);
 
+// Per-window products K_l v -> yk and (sigma dK_l/dsigma) v -> yks (nfft.hip)
+void matvec_parts(Plan& P, const void* v, void* yk, void* yks, hipStream_t s);
+// FP64 sums for the gradient: per window {p.u.D_l, p.K_l u, p.u.Ds_l, p.Ks_l u}, then sum p,
+// sum u, sum p u; result on the host (nfft.hip)
+void gradient_sums(Plan& P, const void* p, const void* u, std::vector<double>& out, hipStream_t s);
+
 // CG (pcg.hip)
 void compute_max_eta(Plan& P, hipStream_t s);
 nld_status run_pcg(Plan& P, double alpha, const void* f, void* u, const nld_pcg_opts& o,
                    nld_pcg_info& info, hipStream_t s);
+nld_status run_adjoint(Plan& P, double alpha, const void* u, const void* g, void* p, double* grad,
+                       const nld_pcg_opts& o, nld_pcg_info& info, hipStream_t s);
 
 }  // namespace nld

@@ -309,6 +309,47 @@ void compute_max_eta(Plan& P, hipStream_t s) {
   P.max_eta = mx - wsum;
 }
 
+nld_status run_adjoint(Plan& P, double alpha, const void* u, const void* g, void* p, double* grad,
+                       const nld_pcg_opts& o, nld_pcg_info& info, hipStream_t s) {
+  // adjoint state: A p = g with the same symmetric operator
+  const nld_status st = run_pcg(P, alpha, g, p, o, info, s);
+  const long long LN = (long long)P.N * P.L;
+  auto alloc = [&](void** b, size_t bytes) {
+    if (!*b) NLD_HIP(hipMallocAsync(b, bytes, s));
+  };
+  alloc(&P.yk, LN * P.elem);
+  alloc(&P.yks, LN * P.elem);
+  alloc(&P.grid_save, (size_t)P.grid_total * P.elem);
+  alloc((void**)&P.adj_part, (size_t)257 * (4 * P.L + 3) * sizeof(double));
+  if (!P.dl) {
+    alloc(&P.dl, LN * P.elem);
+    alloc(&P.dls, LN * P.elem);
+    matvec_parts(P, P.ones, P.dl, P.dls, s);     // per-window degrees K_l 1 and K^s_l 1
+  }
+  matvec_parts(P, u, P.yk, P.yks, s);
+  std::vector<double> sums;
+  gradient_sums(P, p, u, sums, s);
+  const int L = P.L;
+  const double sp = sums[4 * L], su = sums[4 * L + 1], spu = sums[4 * L + 2];
+  double g_la = 0.0;
+  for (int l = 0; l < L; ++l) {
+    double pLu, pLsu;
+    if (P.wins[l].t > 0) {
+      pLu = sums[4 * l] - sums[4 * l + 1];            // p^T (diag(K_l 1) - K_l) u
+      pLsu = sums[4 * l + 2] - sums[4 * l + 3];
+    } else {                                          // K_l = 1 1^T, sigma derivative 0
+      pLu = (double)P.N * spu - sp * su;
+      pLsu = 0.0;
+    }
+    const double gw = -alpha * pLu;
+    grad[1 + L + l] = gw;                             // d J / d w_l
+    grad[1 + l] = -alpha * P.weight[l] * pLsu;        // d J / d log sigma_l
+    g_la += P.weight[l] * gw;                         // alpha scales every weight
+  }
+  grad[0] = g_la;                                     // d J / d log alpha
+  return st;
+}
+
 nld_status run_pcg(Plan& P, double alpha, const void* f, void* u, const nld_pcg_opts& o,
                    nld_pcg_info& info, hipStream_t s) {
   if (!P.have_D) {

@@ -453,6 +453,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   P.wins.assign(L, WinDev{});
   P.info.assign(L, nld_window_info{});
   P.coef_host.assign(L, {});
+  P.sig_t.assign(3 * (size_t)L, 0.0);
   unsigned tile_total = 0;
   long long max_padded = 1;
   long long grid_total = 0;
@@ -514,6 +515,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
         const double sc = 2.0 * a / R[k];
         const double st = sigma * sc;
         p.feat[dd] = c;
+        P.sig_t[3 * (size_t)l + dd] = st;
         p.centre[dd] = 0.5 * (lo[c] + hi[c]);
         p.scale[dd] = sc;
         p.n[dd] = n;
@@ -597,6 +599,30 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     P.wins[l].coef = (const T*)P.coef + (long long)l * 3 * n_max;
     P.wins[l].n_max = n_max;
   }
+  // sigma-derivative multiplier tables, one set per internal dimension d
+  std::vector<T> coef_dv_all(3 * coef_all.size(), (T)0);
+  for (int d = 0; d < 3; ++d) {
+    P.dv_used[d] = false;
+    for (int l = 0; l < L; ++l) {
+      const int n = P.info[l].grid;
+      if (P.wins[l].n[d] == 1 || P.wins[l].t == 0) continue;   // no dimension d: zero tables
+      P.dv_used[d] = true;
+      const double st = P.sig_t[3 * (size_t)l + d];
+      for (int a = 0; a < 3; ++a)
+        for (int q = 0; q < n; ++q) {
+          double c = P.coef_host[l][(long long)a * n + q];
+          if (a == d) {
+            const int kf = (q < n / 2) ? q : q - n;
+            c *= 1.0 - 2.0 * M_PI * M_PI * st * st * (double)kf * kf;
+          }
+          coef_dv_all[(size_t)d * coef_all.size() + ((size_t)l * 3 + a) * n_max + q] = (T)c;
+        }
+    }
+  }
+  P.coef_dv = dalloc<T>((long long)coef_dv_all.size(), s);
+  NLD_HIP(hipMemcpyAsync(P.coef_dv, coef_dv_all.data(), coef_dv_all.size() * sizeof(T),
+                         hipMemcpyHostToDevice, s));
+
   // window polynomials (same cutoff for every window; the shape b depends on M / n)
   std::vector<T> psi_all;   // host staging buffers live until the final synchronisation
   {
@@ -784,6 +810,14 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   NLD_HIP(hipGetLastError());
   P.d_wins = dalloc<WinDev>(L, s);
   NLD_HIP(hipMemcpyAsync(P.d_wins, P.wins.data(), L * sizeof(WinDev), hipMemcpyHostToDevice, s));
+  std::vector<WinDev> wins_dv[3];
+  for (int d = 0; d < 3; ++d) {
+    wins_dv[d] = P.wins;
+    for (int l = 0; l < L; ++l)
+      wins_dv[d][l].coef = (const T*)P.coef_dv + (size_t)d * coef_all.size() + (size_t)l * 3 * n_max;
+    P.d_wins_dv[d] = dalloc<WinDev>(L, s);
+    NLD_HIP(hipMemcpyAsync(P.d_wins_dv[d], wins_dv[d].data(), L * sizeof(WinDev), hipMemcpyHostToDevice, s));
+  }
 
   dfree(d_cp, s);
   dfree(base, s);
@@ -806,7 +840,9 @@ void release_plan(Plan& P) {
   hipStream_t s = P.stream;
   void* bufs[] = {P.d_wins, P.g_idx, P.g_base, P.g_frac, P.coef, P.grid, P.padded, P.tile_slot0,
                   P.tile_nslot, P.ylocal, P.D, P.sumv, P.ones, P.psi, P.d_tjobs, P.d_fjobs, P.d_f3jobs, P.d_conv[0], P.d_conv[1],
-                  P.d_conv[2], P.z, P.r, P.p, P.q, P.red, P.st};
+                  P.d_conv[2], P.z, P.r, P.p, P.q, P.red, P.st, P.coef_dv, P.d_wins_dv[0],
+                  P.d_wins_dv[1], P.d_wins_dv[2], P.grid_save, P.yk, P.yks, P.dl, P.dls,
+                  P.adj_part};
   for (void* b : bufs) dfree(b, s);
   (void)hipStreamSynchronize(s);
 }

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NOCONV", 
 
 # Entry points declared in include/nld.h
 SYMBOLS = ("nfft_plan", "nfft_plan_destroy", "nfft_plan_window_info", "nfft_plan_size",
-           "degree_vector", "anova_matvec", "laplacian_matvec", "pcg_solve",
+           "degree_vector", "anova_matvec", "laplacian_matvec", "pcg_solve", "adjoint_solve",
            "features_from_image", "nld_last_error")
 
 
@@ -87,6 +87,8 @@ def load() -> ctypes.CDLL:
         "anova_matvec": [P, P, P, P],
         "laplacian_matvec": [P, P, P, P],
         "pcg_solve": [P, D, P, P, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo), P],
+        "adjoint_solve": [P, D, P, P, P, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(PcgOpts),
+                          ctypes.POINTER(PcgInfo), P],
         "features_from_image": [P, I32, I32, I32, I32, I32, P, P],
     }
     for name, args in sig.items():
@@ -237,6 +239,24 @@ class Plan:
         return u, info.as_dict()
 
 
+    def adjoint_solve(self, alpha: float, f: torch.Tensor, u: torch.Tensor, g: torch.Tensor,
+                      tol: float = 1e-10, maxit: int = 500, stream=None):
+        """Adjoint solve A p = g and the gradient (see adjoint_solve in nld.h).
+        Returns (p, grad, info) with grad = [dJ/dlog alpha, dJ/dlog sigma_l..., dJ/dw_l...]."""
+        import numpy as np
+        p = torch.empty_like(g)
+        grad = (ctypes.c_double * (1 + 2 * self.L))()
+        opts = PcgOpts(float(tol), int(maxit), 0, 1, 1, 0, 0)
+        info = PcgInfo()
+        st = load().adjoint_solve(self.handle, float(alpha), _vec(f, self.N, self.dtype, "f"),
+                                  _vec(u, self.N, self.dtype, "u"), _vec(g, self.N, self.dtype, "g"),
+                                  _vec(p, self.N, self.dtype, "p"), grad, ctypes.byref(opts),
+                                  ctypes.byref(info), _stream(stream))
+        if st not in (NLD_OK, NLD_E_NOCONV):
+            _check(st)
+        return p, np.array(grad[:], dtype=np.float64), info.as_dict()
+
+
 def nfft_plan(features, windows, sigma, weight, **kw) -> Plan:
     return Plan(features, windows, sigma, weight, **kw)
 
@@ -271,3 +291,41 @@ def window_table(rho: int, with_pos: bool = True):
     wins = [[0, 1, centre]] if with_pos else []
     wins += [rest[s:s + 3] for s in range(0, len(rest), 3)]
     return wins
+
+
+def adjoint_solve(plan: Plan, alpha, f, u, g, **kw):
+    return plan.adjoint_solve(alpha, f, u, g, **kw)
+
+
+class DenoiseSolve(torch.autograd.Function):
+    """u = (I + alpha L(sigma, w))^-1 f with alpha = exp(log_alpha), sigma = exp(log_sigma).
+
+    forward: nfft_plan + pcg_solve; backward: adjoint_solve (one adjoint solve with the same
+    operator plus the sigma-derivative summation).  The features are data: no gradient flows
+    into them; the gradient with respect to f is the adjoint state p.  log_alpha, log_sigma
+    and weight are float64 CPU tensors; f is a GPU tensor of the plan's precision."""
+
+    @staticmethod
+    def forward(ctx, f, log_alpha, log_sigma, weight, features, windows, plan_kw, tol):
+        L = len(windows)
+        sig = torch.exp(log_sigma.detach()).tolist()
+        wts = weight.detach().tolist()
+        plan = Plan(features, windows, sig, wts, **plan_kw)
+        alpha = float(torch.exp(log_alpha.detach()))
+        u, info = plan.pcg_solve(alpha, f, tol=tol)
+        if info["status"] != "OK":
+            raise NldError(NLD_E_NOCONV, f"forward solve: {info}")
+        ctx.plan, ctx.alpha, ctx.tol, ctx.L = plan, alpha, tol, L
+        ctx.save_for_backward(f, u)
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        f, u = ctx.saved_tensors
+        p, grad, info = ctx.plan.adjoint_solve(ctx.alpha, f, u, grad_u.contiguous(), tol=ctx.tol)
+        L = ctx.L
+        g_la = torch.tensor(grad[0], dtype=torch.float64)
+        g_ls = torch.tensor(grad[1:1 + L], dtype=torch.float64)
+        g_w = torch.tensor(grad[1 + L:], dtype=torch.float64)
+        ctx.plan.close()
+        return p, g_la, g_ls, g_w, None, None, None, None

@@ -1,0 +1,111 @@
+"""GPU parity of the adjoint bilevel gradient (HIP path vs the dense oracle and vs finite
+differences of GPU solves)."""
+import numpy as np
+import pytest
+
+from gpu_util import torch_gpu
+from oracle import gradient as OG
+from oracle.features import features_from_image as o_features
+from oracle.features import window_table as o_windows
+from paper_2407_06834_amd.synth import make_image
+
+pytestmark = pytest.mark.gpu
+
+
+def _crops(T=2, n=32, seed=200):
+    out = []
+    for t in range(T):
+        uc, f = make_image(seed + t, n, n, 4, 3, 0.15)
+        out.append((uc, f))
+    return out
+
+
+def _gpu_grad(torch, nld, crops, sig, wts, alpha, M=64, m=8, tol=1e-11):
+    T = len(crops)
+    wins = nld.window_table(1)
+    J = 0.0
+    g = np.zeros(1 + 2 * len(wins))
+    for uc, f in crops:
+        img = torch.tensor(f, dtype=torch.float64, device="cuda")
+        F = nld.features_from_image(img, 1)
+        plan = nld.Plan(F, wins, sig, wts, bandwidth=M, cutoff=m)
+        fv = img.reshape(-1)
+        u, info = plan.pcg_solve(alpha, fv, tol=tol)
+        assert info["status"] == "OK"
+        ucv = torch.tensor(uc.reshape(-1), device="cuda")
+        J += float(torch.sum((u - ucv) ** 2)) / T
+        p, grad, ainfo = plan.adjoint_solve(alpha, fv, u, (2.0 / T) * (u - ucv), tol=tol)
+        assert ainfo["status"] == "OK"
+        g += grad
+        plan.close()
+    return J, g
+
+
+def test_adjoint_gradient_matches_dense_oracle():
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    crops = _crops()
+    sig = [0.1, 0.12, 0.15, 0.2]
+    wts = [1.0, 0.7, 1.3, 0.5]
+    alpha = 0.8
+    J, g = _gpu_grad(torch, nld, crops, sig, wts, alpha)
+    imgs = [(o_features(f, 1), f.reshape(-1), uc.reshape(-1)) for uc, f in crops]
+    Jo, g_la, g_ls, g_w = OG.gradient(imgs, o_windows(1), sig, wts, alpha)
+    ref = np.concatenate([[g_la], g_ls, g_w])
+    assert abs(J - Jo) < 1e-8 * Jo
+    assert np.abs(g - ref).max() < 1e-5 * np.abs(ref).max()
+
+
+def test_adjoint_gradient_matches_finite_differences_of_gpu_solves():
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    crops = _crops(T=1, seed=210)
+    sig = [0.1, 0.1, 0.15, 0.2]
+    wts = [1.0, 1.0, 0.5, 1.5]
+    alpha, h = 1.5, 1e-5
+    J, g = _gpu_grad(torch, nld, crops, sig, wts, alpha)
+    L = len(sig)
+
+    def J_of(la, ls, w):
+        return _gpu_grad(torch, nld, crops, list(np.exp(ls)), list(w), float(np.exp(la)))[0]
+
+    la0, ls0, w0 = np.log(alpha), np.log(sig), np.array(wts)
+    fd = [(J_of(la0 + h, ls0, w0) - J_of(la0 - h, ls0, w0)) / (2 * h)]
+    for l in range(L):
+        e = np.zeros(L)
+        e[l] = h
+        fd.append((J_of(la0, ls0 + e, w0) - J_of(la0, ls0 - e, w0)) / (2 * h))
+    for l in range(L):
+        e = np.zeros(L)
+        e[l] = h
+        fd.append((J_of(la0, ls0, w0 + e) - J_of(la0, ls0, w0 - e)) / (2 * h))
+    fd = np.array(fd)
+    assert np.abs(g - fd).max() < 1e-5 * np.abs(fd).max()
+
+
+def test_autograd_function_fp32():
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    uc, f = make_image(220, 48, 48, 4, 3, 0.15)
+    img = torch.tensor(f, dtype=torch.float32, device="cuda")
+    F = nld.features_from_image(img, 1)
+    wins = nld.window_table(1)
+    la = torch.tensor(0.0, dtype=torch.float64, requires_grad=True)
+    ls = torch.log(torch.full((4,), 0.1, dtype=torch.float64)).requires_grad_()
+    w = torch.ones(4, dtype=torch.float64, requires_grad=True)
+    u = nld.DenoiseSolve.apply(img.reshape(-1), la, ls, w, F, wins, dict(bandwidth=64, cutoff=4), 1e-7)
+    ucv = torch.tensor(uc.reshape(-1), dtype=torch.float32, device="cuda")
+    loss = torch.sum((u - ucv) ** 2)
+    loss.backward()
+    assert la.grad is not None and torch.isfinite(la.grad)
+    assert ls.grad.shape == (4,) and torch.isfinite(ls.grad).all()
+    # the alpha derivative is the weight-weighted sum of the weight derivatives
+    assert abs(float(la.grad) - float(torch.dot(w.detach(), w.grad))) < 1e-6 * abs(float(la.grad))
+    # compare against FP64 with the same parameters
+    img64 = img.double()
+    F64 = nld.features_from_image(img64, 1)
+    la2 = torch.tensor(0.0, dtype=torch.float64, requires_grad=True)
+    u64 = nld.DenoiseSolve.apply(img64.reshape(-1), la2, ls.detach().clone(), w.detach().clone(), F64,
+                                 wins, dict(bandwidth=64, cutoff=8), 1e-11)
+    torch.sum((u64 - ucv.double()) ** 2).backward()
+    assert abs(float(la.grad) - float(la2.grad)) < 1e-3 * abs(float(la2.grad))
