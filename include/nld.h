@@ -95,6 +95,22 @@ typedef struct {
 nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t d,
                      const nld_kernel_desc* desc, hipStream_t s);
 
+/* New kernel widths sigma[L] (> 0) and weights weight[L] (>= 0), host arrays, for an existing
+ * plan: the Fourier multipliers of Sec. 3 (periodic Gaussian coefficients of every window)
+ * and of the width derivative are rewritten, the degree vector is recomputed on next use;
+ * node coordinates, the sort and all schedules are kept, so this costs a few table uploads.
+ * The node compression a and bandwidth M of every window stay as built: if the per-entry
+ * error estimate at the new width, max(exp(-(pi st M / 2)^2), exp(-((1 - 2a) / st)^2)) with
+ * st the width on the torus, exceeds both 1e-2 * matvec_tol and ten times the larger of its
+ * value at the old width and the estimate a new plan with the same M would reach (optimal a),
+ * the call returns NLD_E_STATE and leaves the plan unchanged (build a new plan instead); so
+ * does a window whose bandwidth was autotuned (0 in the descriptor) when the autotuner would
+ * pick another M for the new width.
+ * Blocks until the tables are on the device.  The bilevel learning of Sec. 5.5 changes
+ * (sigma_l, w_l) once per outer step. */
+nld_status nfft_plan_update_kernel(nfft_plan_t plan, const double* sigma, const double* weight,
+                                   hipStream_t s);
+
 /* Release every device buffer of the plan (enqueued on the plan's last stream). */
 nld_status nfft_plan_destroy(nfft_plan_t plan);
 

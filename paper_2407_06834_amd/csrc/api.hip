@@ -139,6 +139,21 @@ nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t 
   return NLD_OK;
 }
 
+nld_status nfft_plan_update_kernel(nfft_plan_t plan, const double* sigma, const double* weight,
+                                   hipStream_t s) {
+  if (!plan || !sigma || !weight) return fail(NLD_E_INVAL, "nfft_plan_update_kernel: null pointer");
+  nld::Plan& P = plan->P;
+  for (int l = 0; l < P.L; ++l) {
+    if (!finite_pos(sigma[l])) return fail(NLD_E_INVAL, "nfft_plan_update_kernel: sigma must be finite and > 0");
+    if (!std::isfinite(weight[l]) || weight[l] < 0.0)
+      return fail(NLD_E_INVAL, "nfft_plan_update_kernel: weights must be finite and >= 0");
+  }
+  return guarded("nfft_plan_update_kernel", [&] {
+    nld::update_kernel(P, sigma, weight, s);
+    return NLD_OK;
+  });
+}
+
 nld_status nfft_plan_destroy(nfft_plan_t plan) {
   if (!plan) return fail(NLD_E_INVAL, "nfft_plan_destroy: null plan");
   nld::release_plan(plan->P);

@@ -128,6 +128,8 @@ struct Plan {
   void* dls = nullptr;             // [L][N] K^s_l 1
   double* adj_part = nullptr;      // reduction partials of the gradient sums
   std::vector<double> sig_t;       // [L][3] scaled widths per internal dimension
+  std::vector<double> scale_t;     // [L][3] node scaling per internal dimension (0: dropped)
+  int n_max = 1;                   // largest grid side over the windows (table stride)
   double psi_err = 0.0;            // max abs error of the window polynomial (plan time check)
   void* grid = nullptr;            // concatenated grids
   long long grid_total = 0;
@@ -182,6 +184,7 @@ void gradient_sums(Plan& P, const void* p, const void* u, std::vector<double>& o
 
 // CG (pcg.hip)
 void compute_max_eta(Plan& P, hipStream_t s);
+void update_kernel(Plan& P, const double* sigma, const double* weight, hipStream_t s);
 nld_status run_pcg(Plan& P, double alpha, const void* f, void* u, const nld_pcg_opts& o,
                    nld_pcg_info& info, hipStream_t s);
 nld_status run_adjoint(Plan& P, double alpha, const void* u, const void* g, void* p, double* grad,

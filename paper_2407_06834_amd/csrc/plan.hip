@@ -413,6 +413,100 @@ void launch_features(const void* img, int n1, int n2, int rho, int with_pos, nld
   NLD_HIP(hipGetLastError());
 }
 
+// Smallest bandwidth from a fixed ladder whose per-entry error estimate is below 1e-2 * tol in
+// every dimension of the window (the largest candidate if none is).
+static int auto_bandwidth(double sigma, const std::vector<double>& R, double tol) {
+  static const int cand[] = {16, 24, 32, 48, 64, 96, 128};
+  for (int c : cand) {
+    double e = 0.0;
+    for (double r : R) e = std::max(e, dim_error(sigma, r, c));
+    if (e <= 1e-2 * tol) return c;
+  }
+  return 128;
+}
+
+// Fourier multipliers of every window from the scaled widths P.sig_t: per internal dimension
+// d the periodic Gaussian coefficients over the squared Kaiser-Bessel factor on |k| <= M/2 - 1
+// (zero elsewhere), and for the sigma derivative the same tables with dimension d's factor
+// multiplied by (1 - 2 pi^2 st_d^2 k^2), so that the sum over d of the three products gives
+// the coefficients b_k (t - 2 pi^2 sum_d st_d^2 k_d^2) of sigma dK/dsigma.
+template <typename T>
+static void upload_tables(Plan& P, std::vector<T>& coef_all, std::vector<T>& coef_dv_all,
+                          hipStream_t s) {
+  const int L = P.L, n_max = P.n_max;
+  P.coef_host.assign(L, {});
+  for (int l = 0; l < L; ++l) {
+    const WinDev& w = P.wins[l];
+    const int n = P.info[l].grid, M = P.info[l].bandwidth;
+    std::vector<double> coef(3LL * n, 0.0);
+    for (int dd = 0; dd < 3; ++dd) {
+      if (w.n[dd] == 1) continue;
+      const double st = P.sig_t[3 * (size_t)l + dd];
+      for (int q = 0; q < n; ++q) {
+        const int kf = (q < n / 2) ? q : q - n;
+        if (std::abs(kf) <= M / 2 - 1) {
+          const double bh = std::sqrt(M_PI) * st * std::exp(-std::pow(M_PI * st * kf, 2));
+          const double ph = kb_fourier(kf, n, w.m, w.b);
+          coef[(long long)dd * n + q] = bh / (ph * ph);
+        }
+      }
+    }
+    P.coef_host[l] = std::move(coef);
+  }
+  coef_all.assign(3LL * n_max * L, (T)0);
+  for (int l = 0; l < L; ++l) {
+    const int n = P.info[l].grid;
+    for (int dd = 0; dd < 3; ++dd)
+      for (int q = 0; q < n; ++q)
+        coef_all[((long long)l * 3 + dd) * n_max + q] = (T)P.coef_host[l][(long long)dd * n + q];
+  }
+  if (!P.coef) P.coef = dalloc<T>((long long)coef_all.size(), s);
+  NLD_HIP(hipMemcpyAsync(P.coef, coef_all.data(), coef_all.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  for (int l = 0; l < L; ++l) {
+    P.wins[l].coef = (const T*)P.coef + (long long)l * 3 * n_max;
+    P.wins[l].n_max = n_max;
+  }
+  coef_dv_all.assign(3 * coef_all.size(), (T)0);
+  for (int d = 0; d < 3; ++d) {
+    P.dv_used[d] = false;
+    for (int l = 0; l < L; ++l) {
+      const int n = P.info[l].grid;
+      if (P.wins[l].n[d] == 1 || P.wins[l].t == 0) continue;   // no dimension d: zero tables
+      P.dv_used[d] = true;
+      const double st = P.sig_t[3 * (size_t)l + d];
+      for (int a = 0; a < 3; ++a)
+        for (int q = 0; q < n; ++q) {
+          double c = P.coef_host[l][(long long)a * n + q];
+          if (a == d) {
+            const int kf = (q < n / 2) ? q : q - n;
+            c *= 1.0 - 2.0 * M_PI * M_PI * st * st * (double)kf * kf;
+          }
+          coef_dv_all[(size_t)d * coef_all.size() + ((size_t)l * 3 + a) * n_max + q] = (T)c;
+        }
+    }
+  }
+  if (!P.coef_dv) P.coef_dv = dalloc<T>((long long)coef_dv_all.size(), s);
+  NLD_HIP(hipMemcpyAsync(P.coef_dv, coef_dv_all.data(), coef_dv_all.size() * sizeof(T),
+                         hipMemcpyHostToDevice, s));
+}
+
+// Device copies of the window descriptors: one with the kernel multipliers, and one per
+// internal dimension with the sigma-derivative multipliers of that dimension.
+template <typename T>
+static void upload_windows(Plan& P, std::vector<WinDev> (&wins_dv)[3], hipStream_t s) {
+  const int L = P.L;
+  const size_t table = 3ULL * P.n_max * L;
+  if (!P.d_wins) P.d_wins = dalloc<WinDev>(L, s);
+  NLD_HIP(hipMemcpyAsync(P.d_wins, P.wins.data(), L * sizeof(WinDev), hipMemcpyHostToDevice, s));
+  for (int d = 0; d < 3; ++d) {
+    wins_dv[d] = P.wins;
+    for (int l = 0; l < L; ++l)
+      wins_dv[d][l].coef = (const T*)P.coef_dv + (size_t)d * table + (size_t)l * 3 * P.n_max;
+    if (!P.d_wins_dv[d]) P.d_wins_dv[d] = dalloc<WinDev>(L, s);
+    NLD_HIP(hipMemcpyAsync(P.d_wins_dv[d], wins_dv[d].data(), L * sizeof(WinDev), hipMemcpyHostToDevice, s));
+  }
+}
+
 template <typename T>
 static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   const long long N = P.N;
@@ -454,6 +548,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   P.info.assign(L, nld_window_info{});
   P.coef_host.assign(L, {});
   P.sig_t.assign(3 * (size_t)L, 0.0);
+  P.scale_t.assign(3 * (size_t)L, 0.0);
   unsigned tile_total = 0;
   long long max_padded = 1;
   long long grid_total = 0;
@@ -476,15 +571,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     const double sigma = P.sigma[l];
     // bandwidth M
     int M = P.bw[l];
-    if (M == 0) {
-      static const int cand[] = {16, 24, 32, 48, 64, 96, 128};
-      M = 128;
-      for (int c : cand) {
-        double e = 0.0;
-        for (double r : R) e = std::max(e, dim_error(sigma, r, c));
-        if (e <= 1e-2 * P.tol) { M = c; break; }
-      }
-    }
+    if (M == 0) M = auto_bandwidth(sigma, R, P.tol);
     int m = P.cutoff;
     if (m == 0) m = fp32 ? 4 : (P.tol >= 1e-9 ? 6 : 8);
     int n = next_pow2((int)std::ceil(P.oversampling * M - 1e-9));
@@ -506,16 +593,15 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     inf.bandwidth = M;
     inf.grid = n;
     inf.cutoff = m;
-    std::vector<double> coef(3LL * n, 0.0);
     for (int dd = 0; dd < 3; ++dd) {
       const int k = dd - (3 - t);   // kept-dimension index of internal dim dd
       if (k >= 0) {
         const int c = kept[k];
         const double a = compression(sigma, R[k], M);
         const double sc = 2.0 * a / R[k];
-        const double st = sigma * sc;
         p.feat[dd] = c;
-        P.sig_t[3 * (size_t)l + dd] = st;
+        P.scale_t[3 * (size_t)l + dd] = sc;
+        P.sig_t[3 * (size_t)l + dd] = sigma * sc;
         p.centre[dd] = 0.5 * (lo[c] + hi[c]);
         p.scale[dd] = sc;
         p.n[dd] = n;
@@ -524,14 +610,6 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
         inf.compression[k] = a;
         inf.lo[k] = lo[c];
         inf.hi[k] = hi[c];
-        for (int q = 0; q < n; ++q) {
-          const int kf = (q < n / 2) ? q : q - n;
-          if (std::abs(kf) <= M / 2 - 1) {
-            const double bh = std::sqrt(M_PI) * st * std::exp(-std::pow(M_PI * st * kf, 2));
-            const double ph = kb_fourier(kf, n, m, b);
-            coef[(long long)dd * n + q] = bh / (ph * ph);
-          }
-        }
       } else {
         p.feat[dd] = -1;
         p.centre[dd] = 0.0;
@@ -583,45 +661,10 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     w.grid_size = (long long)w.n[0] * w.n[1] * w.n[2];
     grid_total += w.grid_size;
     n_max = std::max(n_max, n);
-    P.coef_host[l] = coef;
   }
-  // coefficient tables, stride n_max per dimension
-  std::vector<T> coef_all(3LL * n_max * L, (T)0);
-  for (int l = 0; l < L; ++l) {
-    const int n = P.info[l].grid;
-    for (int dd = 0; dd < 3; ++dd)
-      for (int q = 0; q < n; ++q)
-        coef_all[((long long)l * 3 + dd) * n_max + q] = (T)P.coef_host[l][(long long)dd * n + q];
-  }
-  P.coef = dalloc<T>((long long)coef_all.size(), s);
-  NLD_HIP(hipMemcpyAsync(P.coef, coef_all.data(), coef_all.size() * sizeof(T), hipMemcpyHostToDevice, s));
-  for (int l = 0; l < L; ++l) {
-    P.wins[l].coef = (const T*)P.coef + (long long)l * 3 * n_max;
-    P.wins[l].n_max = n_max;
-  }
-  // sigma-derivative multiplier tables, one set per internal dimension d
-  std::vector<T> coef_dv_all(3 * coef_all.size(), (T)0);
-  for (int d = 0; d < 3; ++d) {
-    P.dv_used[d] = false;
-    for (int l = 0; l < L; ++l) {
-      const int n = P.info[l].grid;
-      if (P.wins[l].n[d] == 1 || P.wins[l].t == 0) continue;   // no dimension d: zero tables
-      P.dv_used[d] = true;
-      const double st = P.sig_t[3 * (size_t)l + d];
-      for (int a = 0; a < 3; ++a)
-        for (int q = 0; q < n; ++q) {
-          double c = P.coef_host[l][(long long)a * n + q];
-          if (a == d) {
-            const int kf = (q < n / 2) ? q : q - n;
-            c *= 1.0 - 2.0 * M_PI * M_PI * st * st * (double)kf * kf;
-          }
-          coef_dv_all[(size_t)d * coef_all.size() + ((size_t)l * 3 + a) * n_max + q] = (T)c;
-        }
-    }
-  }
-  P.coef_dv = dalloc<T>((long long)coef_dv_all.size(), s);
-  NLD_HIP(hipMemcpyAsync(P.coef_dv, coef_dv_all.data(), coef_dv_all.size() * sizeof(T),
-                         hipMemcpyHostToDevice, s));
+  P.n_max = n_max;
+  std::vector<T> coef_all, coef_dv_all;   // host staging, alive until the final synchronisation
+  upload_tables<T>(P, coef_all, coef_dv_all, s);
 
   // window polynomials (same cutoff for every window; the shape b depends on M / n)
   std::vector<T> psi_all;   // host staging buffers live until the final synchronisation
@@ -808,16 +851,8 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(256), 0, s, (unsigned char*)P.st,
                      (long long)sizeof(CgState), (unsigned char)0);
   NLD_HIP(hipGetLastError());
-  P.d_wins = dalloc<WinDev>(L, s);
-  NLD_HIP(hipMemcpyAsync(P.d_wins, P.wins.data(), L * sizeof(WinDev), hipMemcpyHostToDevice, s));
   std::vector<WinDev> wins_dv[3];
-  for (int d = 0; d < 3; ++d) {
-    wins_dv[d] = P.wins;
-    for (int l = 0; l < L; ++l)
-      wins_dv[d][l].coef = (const T*)P.coef_dv + (size_t)d * coef_all.size() + (size_t)l * 3 * n_max;
-    P.d_wins_dv[d] = dalloc<WinDev>(L, s);
-    NLD_HIP(hipMemcpyAsync(P.d_wins_dv[d], wins_dv[d].data(), L * sizeof(WinDev), hipMemcpyHostToDevice, s));
-  }
+  upload_windows<T>(P, wins_dv, s);
 
   dfree(d_cp, s);
   dfree(base, s);
@@ -834,6 +869,65 @@ void build_plan(Plan& P, const void* features, hipStream_t s) {
   P.stream = s;
   if (P.prec == NLD_FP32) build_plan_t<float>(P, features, s);
   else build_plan_t<double>(P, features, s);
+}
+
+// Per-entry error estimate of one dimension with the node compression a kept fixed: the
+// truncation of the Fourier series and the nearest periodic image at distance 1 - 2a.
+static double dim_error_fixed(double st, double a, int M) {
+  const double trunc = std::exp(-std::pow(M_PI * st * M / 2.0, 2));
+  const double wrap = std::exp(-std::pow((1.0 - 2.0 * a) / st, 2));
+  return std::max(trunc, wrap);
+}
+
+template <typename T>
+static void update_kernel_t(Plan& P, const double* sigma, const double* weight, hipStream_t s) {
+  const int L = P.L;
+  // the scaled node coordinates (and with them the sort and every schedule) stay; only the
+  // widths on the torus change, so check that the kept compression and bandwidth still fit
+  std::vector<double> sig_new(P.sig_t);
+  for (int l = 0; l < L; ++l) {
+    const WinDev& w = P.wins[l];
+    const int M = P.info[l].bandwidth;
+    if (P.bw[l] == 0 && w.t > 0) {
+      // an autotuned bandwidth must still be the one the autotuner picks for the new width
+      std::vector<double> R;
+      for (int k = 0; k < w.t; ++k) R.push_back(P.info[l].hi[k] - P.info[l].lo[k]);
+      if (auto_bandwidth(sigma[l], R, P.tol) != M)
+        throw std::runtime_error("nfft_plan_update_kernel: window " + std::to_string(l) +
+                                 " needs another bandwidth for the new sigma");
+    }
+    for (int dd = 0; dd < 3; ++dd) {
+      if (w.n[dd] == 1) continue;
+      const int k = dd - (3 - w.t);
+      const double a = P.info[l].compression[k];
+      const double st_old = P.sig_t[3 * (size_t)l + dd];
+      const double st = sigma[l] * P.scale_t[3 * (size_t)l + dd];
+      const double R = P.info[l].hi[k] - P.info[l].lo[k];
+      const double e_new = dim_error_fixed(st, a, M);
+      const double e_ref = std::max(dim_error_fixed(st_old, a, M), dim_error(sigma[l], R, M));
+      if (e_new > std::max(1e-2 * P.tol, 10.0 * e_ref))
+        throw std::runtime_error("nfft_plan_update_kernel: window " + std::to_string(l) +
+                         " needs a new bandwidth or node scaling for the new sigma");
+      sig_new[3 * (size_t)l + dd] = st;
+    }
+  }
+  P.sig_t = sig_new;
+  for (int l = 0; l < L; ++l) {
+    P.sigma[l] = sigma[l];
+    P.weight[l] = weight[l];
+    P.wins[l].weight = weight[l];
+  }
+  std::vector<T> coef_all, coef_dv_all;
+  upload_tables<T>(P, coef_all, coef_dv_all, s);
+  std::vector<WinDev> wins_dv[3];
+  upload_windows<T>(P, wins_dv, s);
+  NLD_HIP(hipStreamSynchronize(s));
+  P.have_D = false;
+}
+
+void update_kernel(Plan& P, const double* sigma, const double* weight, hipStream_t s) {
+  if (P.prec == NLD_FP32) update_kernel_t<float>(P, sigma, weight, s);
+  else update_kernel_t<double>(P, sigma, weight, s);
 }
 
 void release_plan(Plan& P) {

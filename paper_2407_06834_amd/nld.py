@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NOCONV", 
                 6: "E_STATE"}
 
 # Entry points declared in include/nld.h
-SYMBOLS = ("nfft_plan", "nfft_plan_destroy", "nfft_plan_window_info", "nfft_plan_size",
+SYMBOLS = ("nfft_plan", "nfft_plan_update_kernel", "nfft_plan_destroy", "nfft_plan_window_info", "nfft_plan_size",
            "degree_vector", "anova_matvec", "laplacian_matvec", "pcg_solve", "adjoint_solve",
            "features_from_image", "nld_last_error")
 
@@ -81,6 +81,7 @@ def load() -> ctypes.CDLL:
     sig = {
         "nfft_plan": [ctypes.POINTER(P), P, I64, I32, ctypes.POINTER(KernelDesc), P],
         "nfft_plan_destroy": [P],
+        "nfft_plan_update_kernel": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), P],
         "nfft_plan_window_info": [P, I32, ctypes.POINTER(WindowInfo)],
         "nfft_plan_size": [P, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I32)],
         "degree_vector": [P, P, P],
@@ -185,6 +186,18 @@ class Plan:
                              self.d, ctypes.byref(desc), _stream(stream)))
         self.handle = h
 
+    def update_kernel(self, sigma, weight, stream=None) -> bool:
+        """New (sigma_l, w_l) on the same nodes (see nfft_plan_update_kernel in nld.h).
+        Returns False, leaving the plan unchanged, when the widths need a new plan."""
+        sig = (ctypes.c_double * self.L)(*[float(x) for x in sigma])
+        wt = (ctypes.c_double * self.L)(*[float(x) for x in weight])
+        st = load().nfft_plan_update_kernel(self.handle, sig, wt, _stream(stream))
+        if st == NLD_E_STATE:
+            return False
+        _check(st)
+        self._sig, self._wt = sig, wt
+        return True
+
     def close(self):
         if getattr(self, "handle", None):
             _check(load().nfft_plan_destroy(self.handle))
@@ -259,6 +272,10 @@ class Plan:
 
 def nfft_plan(features, windows, sigma, weight, **kw) -> Plan:
     return Plan(features, windows, sigma, weight, **kw)
+
+
+def nfft_plan_update_kernel(plan: Plan, sigma, weight, **kw) -> bool:
+    return plan.update_kernel(sigma, weight, **kw)
 
 
 def nfft_plan_destroy(plan: Plan):
