@@ -159,6 +159,23 @@ typedef struct {
 nld_status pcg_solve(nfft_plan_t plan, double alpha, const void* f, void* u,
                      const nld_pcg_opts* opts, nld_pcg_info* info, hipStream_t s);
 
+/* Independent solves of `count` plans (distinct handles, equal precision and cutoff), each
+ * (I + alpha[b] L~_b) u_b = f_b with the deflated Jacobi PCG of pcg_solve and the same opts;
+ * f[b] and u[b] are device vectors of plan b's N and precision (u[b] holds u0 if use_u0).
+ * All solves advance together: every stage of an iteration is one launch over all plans, a
+ * chunk of iterations is captured once as a HIP graph and replayed until every solve has
+ * finished, and solves that finish early stop costing work.  Each solve's iterates are
+ * bit-identical to pcg_solve on its plan.  infos[b] (host, count entries) gets each solve's
+ * report; ms_solve is the time from the call until that solve was seen finished.  Computes
+ * the degree vectors of plans that lack them.  Uses each plan's CG work vectors, so a plan
+ * must not be solved elsewhere concurrently.  Blocks until all solves are done; the work runs
+ * on an internal stream ordered after s, and s is ordered after it on return.  Returns
+ * NLD_OK if every solve converged, else the first failing status (infos tell which).
+ * Paper Sec. 4.2-4.3 and 5.3-5.4 (the solver), applied to a batch of images. */
+nld_status pcg_solve_batched(const nfft_plan_t* plans, const double* alpha, const void* const* f,
+                             void* const* u, int32_t count, const nld_pcg_opts* opts,
+                             nld_pcg_info* infos, hipStream_t s);
+
 /* Bilevel gradient by the adjoint method (paper Sec. 2.4 optimality system, Sec. 5.5):
  * given the state u of (I + alpha L~) u = f and g = dJ/du (device, precision of the plan),
  * solves A p = g with the same operator and options as pcg_solve (p: device, out; if

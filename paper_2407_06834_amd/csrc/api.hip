@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <vector>
 #include <algorithm>
 #include <cstring>
 #include <new>
@@ -183,7 +184,7 @@ nld_status degree_vector(nfft_plan_t plan, double* D, hipStream_t s) {
     nld::Plan& P = plan->P;
     P.stream = s;
     if (!P.have_D) {
-      nld::matvec(P, P.ones, P.D, nld::EPI_DEGREE, nullptr, s);
+      nld::matvec(P, P.ones, P.D, nld::EPI_DEGREE, s);
       P.have_D = true;
       nld::compute_max_eta(P, s);
     }
@@ -196,7 +197,7 @@ nld_status anova_matvec(nfft_plan_t plan, const void* v, void* y, hipStream_t s)
   if (!plan || !v || !y) return fail(NLD_E_INVAL, "anova_matvec: null pointer");
   return guarded("anova_matvec", [&] {
     plan->P.stream = s;
-    nld::matvec(plan->P, v, y, nld::EPI_ANOVA, nullptr, s);
+    nld::matvec(plan->P, v, y, nld::EPI_ANOVA, s);
     return NLD_OK;
   });
 }
@@ -207,11 +208,11 @@ nld_status laplacian_matvec(nfft_plan_t plan, const void* v, void* y, hipStream_
     nld::Plan& P = plan->P;
     P.stream = s;
     if (!P.have_D) {
-      nld::matvec(P, P.ones, P.D, nld::EPI_DEGREE, nullptr, s);
+      nld::matvec(P, P.ones, P.D, nld::EPI_DEGREE, s);
       P.have_D = true;
       nld::compute_max_eta(P, s);
     }
-    nld::matvec(P, v, y, nld::EPI_LAPLACIAN, nullptr, s);
+    nld::matvec(P, v, y, nld::EPI_LAPLACIAN, s);
     return NLD_OK;
   });
 }
@@ -239,6 +240,49 @@ nld_status pcg_solve(nfft_plan_t plan, double alpha, const void* f, void* u,
   }
   if (result == NLD_E_NOCONV) nld::set_error("pcg_solve: maximum number of iterations reached");
   if (result == NLD_E_BREAKDOWN) nld::set_error("pcg_solve: CG breakdown (non-finite or non-positive scalar)");
+  return result;
+}
+
+nld_status pcg_solve_batched(const nfft_plan_t* plans, const double* alpha, const void* const* f,
+                             void* const* u, int32_t count, const nld_pcg_opts* opts,
+                             nld_pcg_info* infos, hipStream_t s) {
+  if (!plans || !alpha || !f || !u || !opts || !infos)
+    return fail(NLD_E_INVAL, "pcg_solve_batched: null pointer");
+  if (count < 1 || count > 65536) return fail(NLD_E_INVAL, "pcg_solve_batched: count must be in [1, 65536]");
+  if (!finite_pos(opts->tol) || opts->tol >= 1.0) return fail(NLD_E_INVAL, "pcg_solve_batched: tol must be in (0, 1)");
+  if (opts->maxit < 0) return fail(NLD_E_INVAL, "pcg_solve_batched: maxit must be >= 0");
+  if ((opts->precond != 0 && opts->precond != 1) || (opts->deflate != 0 && opts->deflate != 1) ||
+      (opts->use_u0 != 0 && opts->use_u0 != 1))
+    return fail(NLD_E_INVAL, "pcg_solve_batched: precond, deflate and use_u0 must be 0 or 1");
+  std::vector<nld::Plan*> P(count);
+  for (int b = 0; b < count; ++b) {
+    if (!plans[b] || !f[b] || !u[b]) return fail(NLD_E_INVAL, "pcg_solve_batched: null plan or vector");
+    if (!finite_pos(alpha[b])) return fail(NLD_E_INVAL, "pcg_solve_batched: alpha must be finite and > 0");
+    P[b] = &plans[b]->P;
+    if (P[b]->prec != P[0]->prec) return fail(NLD_E_INVAL, "pcg_solve_batched: plans of different precision");
+    if (P[b]->wins[0].m != P[0]->wins[0].m) return fail(NLD_E_INVAL, "pcg_solve_batched: plans of different cutoff");
+  }
+  {
+    std::vector<nld::Plan*> sorted(P);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+      return fail(NLD_E_INVAL, "pcg_solve_batched: a plan appears twice");
+  }
+  for (int b = 0; b < count; ++b) {
+    std::memset(&infos[b], 0, sizeof(nld_pcg_info));
+    infos[b].relres_true = -1.0;
+  }
+  nld_status result = NLD_OK;
+  nld_status st = guarded("pcg_solve_batched", [&] {
+    result = nld::run_pcg_batched(P.data(), alpha, f, u, count, *opts, infos, s);
+    return NLD_OK;
+  });
+  if (st != NLD_OK) {
+    for (int b = 0; b < count; ++b) infos[b].status = st;
+    return st;
+  }
+  if (result == NLD_E_NOCONV) nld::set_error("pcg_solve_batched: some solve reached the maximum number of iterations");
+  if (result == NLD_E_BREAKDOWN) nld::set_error("pcg_solve_batched: CG breakdown in some solve");
   return result;
 }
 

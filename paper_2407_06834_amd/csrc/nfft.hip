@@ -87,10 +87,18 @@ __device__ __forceinline__ void poly_row(const T* psi, T fr, T* wt) {
 template <typename T, int W, int TD>
 __global__ void __launch_bounds__(kSpreadThreads)
 k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int job0,
-         const int* __restrict__ g_idx, const unsigned* __restrict__ g_base,
-         const T* __restrict__ g_frac, long long LN, const T* __restrict__ v,
-         T* __restrict__ padded, long long slot_stride, const CgState* __restrict__ st) {
-  if (st && st->done) return;
+         const ImgDev* __restrict__ imgs, VecArg in, int check) {
+  const TileJob job = jobs[job0 + blockIdx.x];
+  const WinDev& w = wins[job.win];
+  const ImgDev& im = imgs[w.img];
+  if (check && im.st->done) return;
+  const T* __restrict__ v = vin<T>(im, in);
+  const int* __restrict__ g_idx = w.g_idx;
+  const unsigned* __restrict__ g_base = w.g_base;
+  const T* __restrict__ g_frac = reinterpret_cast<const T*>(w.g_frac);
+  const long long LN = w.LN;
+  T* __restrict__ padded = reinterpret_cast<T*>(w.padded);
+  const long long slot_stride = w.slot_stride;
   constexpr int K = PsiDeg<T>::value + 1;
   constexpr int PAIRS = (TD == 1) ? W : W * W;
   constexpr int NP = (PAIRS + 63) / 64;
@@ -100,8 +108,6 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem_raw);
   __shared__ double s_part[kSpreadWaves];
   __shared__ T s_psi[REG ? 1 : W * K];
-  const TileJob job = jobs[job0 + blockIdx.x];
-  const WinDev& w = wins[job.win];
   const int pe1 = w.pe[1], pe2 = w.pe[2];
   const int cells = w.pe[0] * pe1 * pe2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -238,12 +244,16 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_fold(const WinDev* __restrict__ wins, const FoldJob* __restrict__ jobs,
-       const T* __restrict__ padded, long long slot_stride, const int* __restrict__ tile_slot0,
-       const int* __restrict__ tile_nslot, T* __restrict__ grid, const CgState* __restrict__ st) {
-  if (st && st->done) return;
+       const ImgDev* __restrict__ imgs, int check) {
   const FoldJob job = jobs[blockIdx.x];
-  if ((int)threadIdx.x >= job.ncell) return;
   const WinDev& w = wins[job.win];
+  if (check && imgs[w.img].st->done) return;
+  if ((int)threadIdx.x >= job.ncell) return;
+  const T* __restrict__ padded = reinterpret_cast<const T*>(w.padded);
+  const long long slot_stride = w.slot_stride;
+  const int* __restrict__ tile_slot0 = w.tile_slot0;
+  const int* __restrict__ tile_nslot = w.tile_nslot;
+  T* __restrict__ grid = reinterpret_cast<T*>(w.grid);
   const long long c = job.cell0 + threadIdx.x;
   int ct[3][3], cl[3][3], cn[3];
   {
@@ -296,12 +306,16 @@ k_fold(const WinDev* __restrict__ wins, const FoldJob* __restrict__ jobs,
 // read consecutive padded cells; no barriers, no LDS.
 template <typename T, int TS>
 __global__ void __launch_bounds__(TS * TS)
-k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs,
-        const T* __restrict__ padded, long long slot_stride, const int* __restrict__ tile_slot0,
-        const int* __restrict__ tile_nslot, T* __restrict__ grid, const CgState* __restrict__ st) {
-  if (st && st->done) return;
-  const Fold3Job job = jobs[blockIdx.x];
+k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int job0,
+        const ImgDev* __restrict__ imgs, int check) {
+  const Fold3Job job = jobs[job0 + blockIdx.x];
   const WinDev& w = wins[job.win];
+  if (check && imgs[w.img].st->done) return;
+  const T* __restrict__ padded = reinterpret_cast<const T*>(w.padded);
+  const long long slot_stride = w.slot_stride;
+  const int* __restrict__ tile_slot0 = w.tile_slot0;
+  const int* __restrict__ tile_nslot = w.tile_nslot;
+  T* __restrict__ grid = reinterpret_cast<T*>(w.grid);
   const int x2 = threadIdx.x % TS, x1 = threadIdx.x / TS;
   const int tc2 = job.tile & (w.nts[2] - 1);
   const int tc1 = (job.tile >> w.lnts[2]) & (w.nts[1] - 1);
@@ -425,16 +439,17 @@ template <int N> struct FftShape {
 template <typename T, int N>
 __global__ void __launch_bounds__(256)
 k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int job0, int axis,
-       T* __restrict__ grid, const CgState* __restrict__ st) {
-  if (st && st->done) return;
+       const ImgDev* __restrict__ imgs, int check) {
+  const ConvJob job = jobs[job0 + blockIdx.x];
+  const WinDev& w = wins[job.win];
+  if (check && imgs[w.img].st->done) return;
+  T* __restrict__ grid = reinterpret_cast<T*>(w.grid);
   using S = FftShape<N>;
   constexpr int A = S::A, B = S::B, CL = S::CL, RL = S::RL, SP = S::SP;
   extern __shared__ unsigned char smem_raw[];
   T* stage = reinterpret_cast<T*>(smem_raw);                      // RL * SP reals
   Cx<T>* ex = reinterpret_cast<Cx<T>*>(smem_raw);                 // CL * SP complex (same bytes)
   Cx<T>* tw = reinterpret_cast<Cx<T>*>(smem_raw + (size_t)RL * SP * sizeof(T));  // N twiddles
-  const ConvJob job = jobs[job0 + blockIdx.x];
-  const WinDev& w = wins[job.win];
   for (int q = threadIdx.x; q < N; q += 256) {
     T sn, cs;
     if constexpr (sizeof(T) == 4) sincospif(-2.0f * (float)q / (float)N, &sn, &cs);
@@ -528,15 +543,18 @@ constexpr int kStageMin = 192;
 template <typename T, int W, int TD>
 __global__ void __launch_bounds__(kGatherThreads)
 k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int job0,
-         const int* __restrict__ g_idx, const unsigned* __restrict__ g_base,
-         const T* __restrict__ g_frac, long long N, long long LN, const T* __restrict__ grid,
-         T* __restrict__ ylocal, const CgState* __restrict__ st) {
-  if (st && st->done) return;
-  extern __shared__ unsigned char smem_raw[];
-  T* tile = reinterpret_cast<T*>(smem_raw);
+         const ImgDev* __restrict__ imgs, int check) {
   const TileJob job = jobs[job0 + blockIdx.x];
   const WinDev& w = wins[job.win];
-  const T* h = grid + w.grid_off;
+  if (check && imgs[w.img].st->done) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);
+  const int* __restrict__ g_idx = w.g_idx;
+  const unsigned* __restrict__ g_base = w.g_base;
+  const T* __restrict__ g_frac = reinterpret_cast<const T*>(w.g_frac);
+  const long long LN = w.LN;
+  T* __restrict__ ylocal = reinterpret_cast<T*>(w.ylocal);
+  const T* h = reinterpret_cast<const T*>(w.grid) + w.grid_off;
   const int n0 = w.n[0], n1 = w.n[1], n2 = w.n[2];
   const int pe0 = w.pe[0], pe1 = w.pe[1], pe2 = w.pe[2];
   const int o0 = tile_origin(w, job.tile, 0), o1 = tile_origin(w, job.tile, 1),
@@ -566,7 +584,6 @@ k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     __syncthreads();
     psi = s_psi;
   }
-  const long long ybase = (long long)job.win * N;
   constexpr int K = KP;
   // large rows (FP64, m >= 6): evaluate the middle dimension's weights inside the loop instead of
   // keeping a second register row, to stay within the register file
@@ -614,74 +631,74 @@ k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     } else {
       acc = plane(0);
     }
-    ylocal[ybase + g_idx[p]] = acc;
+    ylocal[g_idx[p]] = acc;
   }
 }
 
 // ---------------------------------------------------------------------------- reduction
 struct ReduceArgs {
-  const void* yl;
-  const double* wts;   // [L] window weights (device)
-  int L;
-  long long N;
-  const void* v;
-  void* out;
-  double* Dout;
-  const double* D;
-  const void* f;
-  CgState* st;
-  double* red;
-  const double* sumv;
+  VecArg in;           // the product's input v
+  VecArg out;          // result vector (unused for EPI_DEGREE and EPI_CG_TRUE)
+  double* Dout;        // EPI_DEGREE: destination if non-null, else the image's D
   int mode;
 };
 
-// sum of v (FP64), for windows whose kernel is the constant 1 1^T
+// sum of v (FP64) per image, for windows whose kernel is the constant 1 1^T
 template <typename T>
-__global__ void __launch_bounds__(1024) k_sum(const T* __restrict__ v, long long N,
-                                              double* __restrict__ out, const CgState* __restrict__ st) {
-  if (st && st->done) return;
+__global__ void __launch_bounds__(1024) k_sum(const ImgDev* __restrict__ imgs, VecArg in, int check) {
+  const ImgDev& im = imgs[blockIdx.y];
+  if (check && im.st->done) return;
+  const T* v = vin<T>(im, in);
   __shared__ double sh[1024];
   double a = 0.0;
-  for (long long i = threadIdx.x; i < N; i += 1024) a += (double)v[i];
+  for (long long i = threadIdx.x; i < im.N; i += 1024) a += (double)v[i];
   sh[threadIdx.x] = a;
   __syncthreads();
   for (int s = 512; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = sh[0];
+  if (threadIdx.x == 0) *im.sumv = sh[0];
 }
 
+// One row of blocks per image (blockIdx.y): the FP64 sum over the image's windows fused with
+// the epilogue; the CG epilogues reduce their sums over the image's nred blocks.
 template <typename T>
-__global__ void __launch_bounds__(kRedThreads) k_reduce(const WinDev* __restrict__ wins, ReduceArgs a) {
-  CgState* st = a.st;
-  if (st && a.mode == EPI_CG_Q && st->done) return;
-  const T* yl = (const T*)a.yl;
-  const T* v = (const T*)a.v;
-  T* out = (T*)a.out;
-  const long long N = a.N;
+__global__ void __launch_bounds__(kRedThreads)
+k_reduce(const WinDev* __restrict__ wins, const ImgDev* __restrict__ imgs, ReduceArgs a) {
+  const ImgDev& im = imgs[blockIdx.y];
+  const bool cg = a.mode >= EPI_CG_Q;
+  CgState* st = im.st;
+  if (a.mode == EPI_CG_Q && st->done) return;
+  if (cg && blockIdx.x >= (unsigned)im.nred) return;
+  const unsigned nb = cg ? (unsigned)im.nred : gridDim.x;
+  const T* v = vin<T>(im, a.in);
+  const long long N = im.N;
+  const int l0 = im.win0, l1 = im.win0 + im.L;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  const double alpha = st ? st->alpha : 0.0;
-  const double mean_f = st ? st->mean_f : 0.0;
+  const double alpha = cg ? st->alpha : 0.0;
+  const double mean_f = cg ? st->mean_f : 0.0;
+  const T* f = cg ? reinterpret_cast<const T*>(im.vec[V_F]) : nullptr;
   for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < N;
-       i += (long long)gridDim.x * kRedThreads) {
+       i += (long long)nb * kRedThreads) {
     double y = 0.0;
-    for (int l = 0; l < a.L; ++l)
-      y += wins[l].weight * (wins[l].t > 0 ? (double)yl[(long long)l * N + i] : *a.sumv);
+    for (int l = l0; l < l1; ++l)
+      y += wins[l].weight *
+           (wins[l].t > 0 ? (double)reinterpret_cast<const T*>(wins[l].ylocal)[i] : *im.sumv);
     switch (a.mode) {
       case EPI_ANOVA:
-        out[i] = (T)y;
+        vout<T>(im, a.out)[i] = (T)y;
         break;
       case EPI_LAPLACIAN:
-        out[i] = (T)(a.D[i] * (double)v[i] - y);
+        vout<T>(im, a.out)[i] = (T)(im.D[i] * (double)v[i] - y);
         break;
       case EPI_DEGREE:
-        a.Dout[i] = y;
+        (a.Dout ? a.Dout : im.D)[i] = y;
         break;
       case EPI_CG_Q: {
         const double vi = (double)v[i];
-        const double q = vi + alpha * (a.D[i] * vi - y);
-        out[i] = (T)q;
+        const double q = vi + alpha * (im.D[i] * vi - y);
+        vout<T>(im, a.out)[i] = (T)q;
         s0 += vi * q;
         s1 += q;
         s2 += vi;
@@ -690,19 +707,19 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(const WinDev* __restrict
       case EPI_CG_INIT:
       case EPI_CG_TRUE: {
         const double vi = (double)v[i];
-        const double b = (double)((const T*)a.f)[i] - mean_f;
-        const double r = b - (vi + alpha * (a.D[i] * vi - y));
-        if (a.mode == EPI_CG_INIT) out[i] = (T)r;
+        const double b = (double)f[i] - mean_f;
+        const double r = b - (vi + alpha * (im.D[i] * vi - y));
+        if (a.mode == EPI_CG_INIT) vout<T>(im, a.out)[i] = (T)r;
         s0 += r;
         s1 += (a.mode == EPI_CG_INIT) ? b * b : r * r;
         break;
       }
     }
   }
-  if (a.mode < EPI_CG_Q) return;
+  if (!cg) return;
   const double vals[3] = {s0, s1, s2};
   double tot[3];
-  if (!grid_reduce<3>(vals, a.red, &st->ticket[0], tot)) return;
+  if (!grid_reduce<3>(vals, im.red, &st->ticket[0], tot, nb)) return;
   if (threadIdx.x != 0) return;
   const double dN = (double)N;
   if (a.mode == EPI_CG_Q) {
@@ -731,92 +748,92 @@ inline unsigned grid_for(long long n, int threads = 256) {
   return (unsigned)std::max<long long>(1, std::min<long long>(b, 65536));
 }
 
+template <typename K>
+void allow_lds(K k, size_t lds) {
+  if (lds > 65536)
+    NLD_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+}
+
 template <typename T, int W>
-void launch_tiles(Plan& P, const void* v, const CgState* st, hipStream_t s, bool gather) {
-  const size_t lds = (size_t)P.max_padded * (gather ? sizeof(T) : sizeof(double));
-  const long long LN = (long long)P.N * P.L;
+void launch_tiles(const LaunchSet& ls, VecArg in, int check, hipStream_t s, bool gather) {
+  const size_t lds = (size_t)ls.max_padded * (gather ? sizeof(T) : sizeof(double));
   for (int g = 0; g < 3; ++g) {
-    const int j0 = P.tjob_begin[g], nj = P.tjob_begin[g + 1] - j0;
+    const int j0 = ls.tjob_begin[g], nj = ls.tjob_begin[g + 1] - j0;
     if (nj == 0) continue;
     if (!gather) {
       auto k = (g == 0) ? k_spread<T, W, 1> : (g == 1) ? k_spread<T, W, 2> : k_spread<T, W, 3>;
-      if (lds > 65536) NLD_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      hipLaunchKernelGGL(k, dim3(nj), dim3(kSpreadThreads), lds, s, P.d_wins, P.d_tjobs, j0, P.g_idx,
-                         P.g_base, (const T*)P.g_frac, LN, (const T*)v, (T*)P.padded, P.slot_stride, st);
+      allow_lds(k, lds);
+      hipLaunchKernelGGL(k, dim3(nj), dim3(kSpreadThreads), lds, s, ls.d_wins, ls.d_tjobs, j0,
+                         ls.d_imgs, in, check);
     } else {
       auto k = (g == 0) ? k_gather<T, W, 1> : (g == 1) ? k_gather<T, W, 2> : k_gather<T, W, 3>;
-      if (lds > 65536) NLD_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      hipLaunchKernelGGL(k, dim3(nj), dim3(kGatherThreads), lds, s, P.d_wins, P.d_tjobs, j0, P.g_idx,
-                         P.g_base, (const T*)P.g_frac, (long long)P.N, LN, (const T*)P.grid,
-                         (T*)P.ylocal, st);
+      allow_lds(k, lds);
+      hipLaunchKernelGGL(k, dim3(nj), dim3(kGatherThreads), lds, s, ls.d_wins, ls.d_tjobs, j0,
+                         ls.d_imgs, check);
     }
     NLD_HIP(hipGetLastError());
   }
 }
 
 template <typename T>
-void tiles_dispatch(Plan& P, const void* v, const CgState* st, hipStream_t s, bool gather) {
-  switch (P.wins[0].m) {
-    case 1: launch_tiles<T, 2>(P, v, st, s, gather); break;
-    case 2: launch_tiles<T, 4>(P, v, st, s, gather); break;
-    case 3: launch_tiles<T, 6>(P, v, st, s, gather); break;
-    case 4: launch_tiles<T, 8>(P, v, st, s, gather); break;
-    case 5: launch_tiles<T, 10>(P, v, st, s, gather); break;
-    case 6: launch_tiles<T, 12>(P, v, st, s, gather); break;
-    case 7: launch_tiles<T, 14>(P, v, st, s, gather); break;
-    case 8: launch_tiles<T, 16>(P, v, st, s, gather); break;
+void tiles_dispatch(const LaunchSet& ls, VecArg in, int check, hipStream_t s, bool gather) {
+  switch (ls.m) {
+    case 1: launch_tiles<T, 2>(ls, in, check, s, gather); break;
+    case 2: launch_tiles<T, 4>(ls, in, check, s, gather); break;
+    case 3: launch_tiles<T, 6>(ls, in, check, s, gather); break;
+    case 4: launch_tiles<T, 8>(ls, in, check, s, gather); break;
+    case 5: launch_tiles<T, 10>(ls, in, check, s, gather); break;
+    case 6: launch_tiles<T, 12>(ls, in, check, s, gather); break;
+    case 7: launch_tiles<T, 14>(ls, in, check, s, gather); break;
+    case 8: launch_tiles<T, 16>(ls, in, check, s, gather); break;
     default: throw std::invalid_argument("cutoff out of range");
   }
 }
 
 template <typename T, int N>
-void launch_conv(Plan& P, const WinDev* wins, int ax, int j0, int nj, const CgState* st, hipStream_t s) {
+void launch_conv(const LaunchSet& ls, int ax, int j0, int nj, int check, hipStream_t s) {
   using S = FftShape<N>;
   const size_t lds = (size_t)S::RL * S::SP * sizeof(T) + (size_t)N * 2 * sizeof(T);
-  if (lds > 65536)
-    NLD_HIP(hipFuncSetAttribute((const void*)k_conv<T, N>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((k_conv<T, N>), dim3(nj), dim3(256), lds, s, wins, P.d_conv[ax], j0, ax,
-                     (T*)P.grid, st);
+  allow_lds(k_conv<T, N>, lds);
+  hipLaunchKernelGGL((k_conv<T, N>), dim3(nj), dim3(256), lds, s, ls.d_wins, ls.d_conv[ax], j0, ax,
+                     ls.d_imgs, check);
   NLD_HIP(hipGetLastError());
 }
 
 template <typename T>
-void conv_all(Plan& P, const WinDev* wins, const CgState* st, hipStream_t s) {
+void conv_all(const LaunchSet& ls, int check, hipStream_t s) {
   for (int ax = 2; ax >= 0; --ax) {
     for (int gi = 0; gi < 4; ++gi) {
-      const int j0 = P.conv_begin[ax][gi], nj = P.conv_begin[ax][gi + 1] - j0;
+      const int j0 = ls.conv_begin[ax][gi], nj = ls.conv_begin[ax][gi + 1] - j0;
       if (nj == 0) continue;
       switch (gi) {
-        case 0: launch_conv<T, 32>(P, wins, ax, j0, nj, st, s); break;
-        case 1: launch_conv<T, 64>(P, wins, ax, j0, nj, st, s); break;
-        case 2: launch_conv<T, 128>(P, wins, ax, j0, nj, st, s); break;
-        default: launch_conv<T, 256>(P, wins, ax, j0, nj, st, s); break;
+        case 0: launch_conv<T, 32>(ls, ax, j0, nj, check, s); break;
+        case 1: launch_conv<T, 64>(ls, ax, j0, nj, check, s); break;
+        case 2: launch_conv<T, 128>(ls, ax, j0, nj, check, s); break;
+        default: launch_conv<T, 256>(ls, ax, j0, nj, check, s); break;
       }
     }
   }
 }
 
 template <typename T>
-void spread_fold(Plan& P, const void* v, const CgState* st, hipStream_t s) {
-  if (P.has_flat) {
-    hipLaunchKernelGGL(k_sum<T>, dim3(1), dim3(1024), 0, s, (const T*)v, (long long)P.N, P.sumv, st);
+void spread_fold(const LaunchSet& ls, VecArg in, int check, hipStream_t s) {
+  if (ls.has_flat) {
+    hipLaunchKernelGGL(k_sum<T>, dim3(1, ls.n_imgs), dim3(1024), 0, s, ls.d_imgs, in, check);
     NLD_HIP(hipGetLastError());
   }
-  tiles_dispatch<T>(P, v, st, s, false);
-  if (P.n_f3jobs > 0) {
-    if (P.f3_ts == 16)
-      hipLaunchKernelGGL((k_fold3<T, 16>), dim3(P.n_f3jobs), dim3(256), 0, s, P.d_wins, P.d_f3jobs,
-                         (const T*)P.padded, P.slot_stride, P.tile_slot0, P.tile_nslot, (T*)P.grid, st);
-    else if (P.f3_ts == 8)
-      hipLaunchKernelGGL((k_fold3<T, 8>), dim3(P.n_f3jobs), dim3(64), 0, s, P.d_wins, P.d_f3jobs,
-                         (const T*)P.padded, P.slot_stride, P.tile_slot0, P.tile_nslot, (T*)P.grid, st);
-    else
-      throw std::runtime_error("internal: unsupported 3-D tile size");
-    NLD_HIP(hipGetLastError());
-  }
-  if (P.n_fjobs > 0) {
-    hipLaunchKernelGGL(k_fold<T>, dim3(P.n_fjobs), dim3(256), 0, s, P.d_wins, P.d_fjobs,
-                       (const T*)P.padded, P.slot_stride, P.tile_slot0, P.tile_nslot, (T*)P.grid, st);
+  tiles_dispatch<T>(ls, in, check, s, false);
+  const int n8 = ls.f3_begin[1] - ls.f3_begin[0], n16 = ls.f3_begin[2] - ls.f3_begin[1];
+  if (n8 > 0)
+    hipLaunchKernelGGL((k_fold3<T, 8>), dim3(n8), dim3(64), 0, s, ls.d_wins, ls.d_f3jobs,
+                       ls.f3_begin[0], ls.d_imgs, check);
+  if (n16 > 0)
+    hipLaunchKernelGGL((k_fold3<T, 16>), dim3(n16), dim3(256), 0, s, ls.d_wins, ls.d_f3jobs,
+                       ls.f3_begin[1], ls.d_imgs, check);
+  NLD_HIP(hipGetLastError());
+  if (ls.n_fjobs > 0) {
+    hipLaunchKernelGGL(k_fold<T>, dim3(ls.n_fjobs), dim3(256), 0, s, ls.d_wins, ls.d_fjobs,
+                       ls.d_imgs, check);
     NLD_HIP(hipGetLastError());
   }
 }
@@ -845,17 +862,20 @@ template <typename T>
 void matvec_parts_t(Plan& P, const void* v, void* yk, void* yks, hipStream_t s) {
   const long long LN = (long long)P.N * P.L;
   const size_t gbytes = (size_t)P.grid_total * sizeof(T);
-  spread_fold<T>(P, v, nullptr, s);
+  const VecArg in{v, 0};
+  spread_fold<T>(P.ls, in, 0, s);
   NLD_HIP(hipMemcpyAsync(P.grid_save, P.grid, gbytes, hipMemcpyDeviceToDevice, s));
-  conv_all<T>(P, P.d_wins, nullptr, s);
-  tiles_dispatch<T>(P, v, nullptr, s, true);
+  conv_all<T>(P.ls, 0, s);
+  tiles_dispatch<T>(P.ls, in, 0, s, true);
   NLD_HIP(hipMemcpyAsync(yk, P.ylocal, LN * sizeof(T), hipMemcpyDeviceToDevice, s));
   bool first = true;
   for (int d = 0; d < 3; ++d) {
     if (!P.dv_used[d]) continue;
+    LaunchSet lsd = P.ls;
+    lsd.d_wins = P.d_wins_dv[d];
     NLD_HIP(hipMemcpyAsync(P.grid, P.grid_save, gbytes, hipMemcpyDeviceToDevice, s));
-    conv_all<T>(P, P.d_wins_dv[d], nullptr, s);
-    tiles_dispatch<T>(P, v, nullptr, s, true);
+    conv_all<T>(lsd, 0, s);
+    tiles_dispatch<T>(lsd, in, 0, s, true);
     hipLaunchKernelGGL(k_axpy_windows<T>, dim3(grid_for(LN)), dim3(256), 0, s, (const T*)P.ylocal,
                        (T*)yks, LN, first ? 1 : 0);
     NLD_HIP(hipGetLastError());
@@ -933,29 +953,21 @@ void gradient_sums_t(Plan& P, const void* p, const void* u, std::vector<double>&
 }
 
 template <typename T>
-void matvec_t(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hipStream_t s) {
-  const bool cg = (epi == EPI_CG_Q || epi == EPI_CG_INIT || epi == EPI_CG_TRUE);
-  // only the iteration's product stops early once the solve has finished
-  const CgState* st = (epi == EPI_CG_Q) ? P.st : nullptr;
-  spread_fold<T>(P, v, st, s);
-  conv_all<T>(P, P.d_wins, st, s);
-  tiles_dispatch<T>(P, v, st, s, true);
+void matvec_set_t(const LaunchSet& ls, VecArg in, VecArg out, double* Dout, Epilogue epi,
+                  hipStream_t s) {
+  // only the iteration's product stops early once a solve has finished
+  const int check = (epi == EPI_CG_Q) ? 1 : 0;
+  spread_fold<T>(ls, in, check, s);
+  conv_all<T>(ls, check, s);
+  tiles_dispatch<T>(ls, in, check, s, true);
   ReduceArgs a;
-  a.yl = P.ylocal;
-  a.wts = nullptr;
-  a.L = P.L;
-  a.N = P.N;
-  a.v = v;
+  a.in = in;
   a.out = out;
-  a.Dout = (epi == EPI_DEGREE) ? (double*)out : nullptr;
-  a.D = P.D;
-  a.f = f;
-  a.st = cg ? P.st : nullptr;
-  a.red = P.red;
-  a.sumv = P.sumv;
+  a.Dout = Dout;
   a.mode = (int)epi;
-  const unsigned nb = (epi >= EPI_CG_Q) ? red_blocks(P.N) : grid_for(P.N, kRedThreads);
-  hipLaunchKernelGGL(k_reduce<T>, dim3(nb), dim3(kRedThreads), 0, s, P.d_wins, a);
+  const unsigned nb = (epi >= EPI_CG_Q) ? (unsigned)ls.max_nred : grid_for(ls.max_N, kRedThreads);
+  hipLaunchKernelGGL(k_reduce<T>, dim3(nb, ls.n_imgs), dim3(kRedThreads), 0, s, ls.d_wins,
+                     ls.d_imgs, a);
   NLD_HIP(hipGetLastError());
 }
 
@@ -971,9 +983,24 @@ void gradient_sums(Plan& P, const void* p, const void* u, std::vector<double>& o
   else gradient_sums_t<double>(P, p, u, out, s);
 }
 
-void matvec(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hipStream_t s) {
-  if (P.prec == NLD_FP32) matvec_t<float>(P, v, out, epi, f, s);
-  else matvec_t<double>(P, v, out, epi, f, s);
+void matvec_set(const LaunchSet& ls, VecArg in, VecArg out, double* Dout, Epilogue epi,
+                hipStream_t s) {
+  if (ls.prec == NLD_FP32) matvec_set_t<float>(ls, in, out, Dout, epi, s);
+  else matvec_set_t<double>(ls, in, out, Dout, epi, s);
+}
+
+void matvec(Plan& P, const void* v, void* out, Epilogue epi, hipStream_t s) {
+  VecArg in{v, V_P}, o{out, V_Q};
+  double* Dout = nullptr;
+  if (epi == EPI_CG_INIT || epi == EPI_CG_TRUE) {
+    in.sel = V_Z;
+    o.sel = V_R;
+  }
+  if (epi == EPI_DEGREE) {
+    Dout = static_cast<double*>(out);
+    o.ext = nullptr;
+  }
+  matvec_set(P.ls, in, o, Dout, epi, s);
 }
 
 }  // namespace nld

@@ -28,10 +28,11 @@ __device__ __forceinline__ double kb_psi(double delta, double m, double b, doubl
 // threads' values with a fixed tree, writes one partial per value, and the last block to
 // finish (agent-scope ticket) sums the partials in block order.  Returns true in the last
 // block, with the totals in out[] for every thread of that block.  Block size must be
-// kRedThreads; the ticket is reset by the last block.
+// kRedThreads; nblocks blocks (blockIdx.x < nblocks) take part; the ticket is reset by the
+// last block.
 template <int NS>
 __device__ bool grid_reduce(const double (&v)[NS], double* red, unsigned* ticket,
-                            double (&out)[NS]) {
+                            double (&out)[NS], unsigned nblocks) {
   __shared__ double sh[NS][kRedThreads];
   __shared__ int last;
   const int t = threadIdx.x;
@@ -46,14 +47,14 @@ __device__ bool grid_reduce(const double (&v)[NS], double* red, unsigned* ticket
     for (int k = 0; k < NS; ++k) red[(size_t)blockIdx.x * 8 + k] = sh[k][0];
     __threadfence();
     const unsigned prev = atomicAdd(ticket, 1u);
-    last = (prev == gridDim.x - 1) ? 1 : 0;
+    last = (prev == nblocks - 1) ? 1 : 0;
   }
   __syncthreads();
   if (!last) return false;
   __threadfence();
   double acc[NS];
   for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-  for (unsigned b = t; b < gridDim.x; b += kRedThreads)
+  for (unsigned b = t; b < nblocks; b += kRedThreads)
     for (int k = 0; k < NS; ++k)
       acc[k] += __hip_atomic_load(&red[(size_t)b * 8 + k], __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
@@ -75,6 +76,15 @@ inline unsigned red_blocks(long long n) {
   if (b > kRedBlocks) b = kRedBlocks;
   if (b < 1) b = 1;
   return (unsigned)b;
+}
+
+template <typename T>
+__device__ __forceinline__ const T* vin(const ImgDev& im, VecArg a) {
+  return a.ext ? reinterpret_cast<const T*>(a.ext) : reinterpret_cast<const T*>(im.vec[a.sel]);
+}
+template <typename T>
+__device__ __forceinline__ T* vout(const ImgDev& im, VecArg a) {
+  return a.ext ? reinterpret_cast<T*>(const_cast<void*>(a.ext)) : reinterpret_cast<T*>(im.vec[a.sel]);
 }
 
 }  // namespace nld

@@ -47,6 +47,39 @@ struct WinDev {
   const void* coef;    // [3][n_max] per-dimension Fourier multipliers (precision T)
   int n_max;
   const void* psi;     // [2m][deg + 1] window polynomial per tap (precision T), see psi_deg
+  // buffers of the plan that owns the window, so that windows of several plans share launches
+  int img;             // index of the window's image in the launch's image table
+  int wl;              // index of the window in its plan
+  long long N;         // nodes of the plan
+  long long LN;        // N L of the plan: stride of the coordinate planes of g_frac
+  const int* g_idx;    // the plan's sorted node lists (positions are plan-global)
+  const unsigned* g_base;
+  const void* g_frac;
+  void* grid;          // the plan's concatenated grids (this window at grid_off)
+  void* padded;        // the plan's padded-tile slots
+  long long slot_stride;
+  const int* tile_slot0;   // indexed by the plan's global tile id (tile_off + tile)
+  const int* tile_nslot;
+  void* ylocal;        // [N] this window's result
+};
+
+// Per-image (per-solve) data of a launch: vectors, degree, CG state and reduction scratch.
+enum VecSel { V_Z = 0, V_R = 1, V_P = 2, V_Q = 3, V_F = 4, V_U = 5, V_ONES = 6, kNumVec = 7 };
+struct CgState;
+struct ImgDev {
+  long long N;
+  int win0, L;         // the image's windows in the launch's window table
+  int nred;            // blocks of the image's FP64 reductions
+  void* vec[kNumVec];  // CG vectors z, r, p, q, right-hand side f, solution u, ones
+  double* D;           // degree vector
+  double* sumv;        // sum of the input (windows without kept dimensions)
+  CgState* st;
+  double* red;         // reduction partials [nred][8]
+};
+// A vector operand: ext if non-null (launches over a single image), else the image's vec[sel].
+struct VecArg {
+  const void* ext;
+  int sel;
 };
 
 // Degree of the per-tap polynomial that replaces the window evaluation: the scaled
@@ -86,6 +119,28 @@ struct CgState {
   double sum_pinv;     // sum_i 1 / P_i
   int iters, maxit, done, status, precond, deflate;
   unsigned int ticket[8];
+};
+
+// Everything one set of launches needs: the window table, the schedules and the image table.
+// A plan has one over its own windows (one image); a batch concatenates those of its plans.
+struct LaunchSet {
+  nld_prec prec = NLD_FP32;
+  int m = 4;                                    // cutoff (equal for every window of the set)
+  const WinDev* d_wins = nullptr;
+  const TileJob* d_tjobs = nullptr;
+  int tjob_begin[4] = {0, 0, 0, 0};             // group g: windows with t = g + 1
+  int max_padded = 1;                           // largest padded tile (cells)
+  const Fold3Job* d_f3jobs = nullptr;
+  int f3_begin[3] = {0, 0, 0};                  // tile extent 8: [0], [1]); 16: [1], [2])
+  const FoldJob* d_fjobs = nullptr;
+  int n_fjobs = 0;
+  const ConvJob* d_conv[3] = {nullptr, nullptr, nullptr};
+  int conv_begin[3][5] = {{0}};                 // per axis, grid size n = 32 << g
+  ImgDev* d_imgs = nullptr;
+  int n_imgs = 0;
+  long long max_N = 0;
+  int max_nred = 1;
+  bool has_flat = false;
 };
 
 // Host-side plan
@@ -161,6 +216,16 @@ struct Plan {
   double* red = nullptr;           // reduction partials [kRedBlocks][8]
   CgState* st = nullptr;           // device CG state
   CgState* st_host = nullptr;      // pinned mirror
+  // launch description of this plan alone, its image table and a pinned host mirror of it
+  LaunchSet ls;
+  ImgDev* d_img = nullptr;
+  ImgDev* img_host = nullptr;
+  // host copies of the schedules (a batch concatenates them)
+  std::vector<TileJob> h_tjobs;
+  std::vector<Fold3Job> h_f3jobs;
+  std::vector<FoldJob> h_fjobs;
+  std::vector<ConvJob> h_conv[3];
+  int tile3 = 0;                   // requested tile extent of 3-D windows (0: default)
 };
 
 // ------------------------------------------------------------------ launchers
@@ -173,8 +238,14 @@ void launch_features(const void* img, int n1, int n2, int rho, int with_pos, nld
 // fast summation (nfft.hip)
 enum Epilogue { EPI_ANOVA = 0, EPI_LAPLACIAN = 1, EPI_DEGREE = 2, EPI_CG_Q = 3, EPI_CG_INIT = 4,
                 EPI_CG_TRUE = 5 };
-// Runs the per-window fast summations on v and the window reduction with the epilogue.
-void matvec(Plan& P, const void* v, void* out, Epilogue epi, const void* f, hipStream_t s);
+// Runs the per-window fast summations on the input of every image of the set and the window
+// reduction with the epilogue (EPI_DEGREE writes Dout if given, else each image's D).  The
+// iteration product (EPI_CG_Q) skips images whose solve has finished.
+void matvec_set(const LaunchSet& ls, VecArg in, VecArg out, double* Dout, Epilogue epi,
+                hipStream_t s);
+// Single-plan form with external vectors (v, out may be null to use the plan's CG vectors
+// through the selectors of the epilogue).
+void matvec(Plan& P, const void* v, void* out, Epilogue epi, hipStream_t s);
 
 // Per-window products K_l v -> yk and (sigma dK_l/dsigma) v -> yks (nfft.hip)
 void matvec_parts(Plan& P, const void* v, void* yk, void* yks, hipStream_t s);
@@ -189,5 +260,9 @@ nld_status run_pcg(Plan& P, double alpha, const void* f, void* u, const nld_pcg_
                    nld_pcg_info& info, hipStream_t s);
 nld_status run_adjoint(Plan& P, double alpha, const void* u, const void* g, void* p, double* grad,
                        const nld_pcg_opts& o, nld_pcg_info& info, hipStream_t s);
+// Independent solves of several plans with one launch per stage (batch.hip)
+nld_status run_pcg_batched(Plan* const* plans, const double* alpha, const void* const* f,
+                           void* const* u, int count, const nld_pcg_opts& o, nld_pcg_info* infos,
+                           hipStream_t s);
 
 }  // namespace nld

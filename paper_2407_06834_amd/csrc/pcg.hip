@@ -28,22 +28,29 @@ __device__ __forceinline__ double pinv(const CgState* st, const double* D, long 
   return st->precond ? 1.0 / (1.0 + st->alpha * (D[i] - st->wsum)) : 1.0;
 }
 
+// Every CG kernel runs one row of blocks per image (blockIdx.y); the reductions of an image use
+// its first nred blocks, so an image's sums do not depend on the other images of the launch.
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
-k_cg_stats(const T* __restrict__ f, const T* __restrict__ u0, const double* __restrict__ D,
-           long long N, CgState* st, double* red) {
+k_cg_stats(const ImgDev* __restrict__ imgs, int u0sel) {
+  const ImgDev& im = imgs[blockIdx.y];
+  if (blockIdx.x >= (unsigned)im.nred) return;
+  CgState* st = im.st;
+  const T* f = reinterpret_cast<const T*>(im.vec[V_F]);
+  const T* u0 = reinterpret_cast<const T*>(im.vec[u0sel]);
+  const long long N = im.N;
   const T f0 = f[0];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < N;
-       i += (long long)gridDim.x * kRedThreads) {
+       i += (long long)im.nred * kRedThreads) {
     s0 += (double)f[i];
     s1 += (double)u0[i];
     s2 += (f[i] != f0) ? 1.0 : 0.0;
-    s3 += pinv<T>(st, D, i);
+    s3 += pinv<T>(st, im.D, i);
   }
   const double vals[4] = {s0, s1, s2, s3};
   double tot[4];
-  if (!grid_reduce<4>(vals, red, &st->ticket[1], tot)) return;
+  if (!grid_reduce<4>(vals, im.red, &st->ticket[1], tot, im.nred)) return;
   if (threadIdx.x != 0) return;
   st->sum_pinv = tot[3];
   st->mean_f = st->deflate ? tot[0] / (double)N : 0.0;
@@ -56,22 +63,18 @@ k_cg_stats(const T* __restrict__ f, const T* __restrict__ u0, const double* __re
 }
 
 template <typename T>
-__global__ void k_cg_z0(const T* __restrict__ u0, T* __restrict__ z, long long N,
-                        const CgState* __restrict__ st) {
+__global__ void k_cg_z0(const ImgDev* __restrict__ imgs, int u0sel) {
+  const ImgDev& im = imgs[blockIdx.y];
+  const CgState* st = im.st;
   if (st->done) return;
+  const T* u0 = reinterpret_cast<const T*>(im.vec[u0sel]);
+  T* z = reinterpret_cast<T*>(im.vec[V_Z]);
   const double mu = st->mean_u0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < im.N;
        i += (long long)gridDim.x * blockDim.x)
     z[i] = (T)((double)u0[i] - mu);
 }
 
-// Residual bookkeeping from sums over the stored residual r (precision T):
-//   tot = {sum r^2, sum t, sum r t, sum r},  t = r / P.
-// The stored r may carry a rounding-level component along 1; it is removed here analytically
-// (c = mean(r), r~ = r - c) and from the stored vector by the next direction kernel, so the
-// residual norm, rho = <r~, Pi(r~ / P)> and the projected preconditioned residual all refer
-// to r~ in the complement of 1.  (Without this the constant component, which the updates
-// never reduce, puts a floor under the residual in FP32.)
 __device__ __forceinline__ void finish_residual(CgState* st, const double (&tot)[4], long long N,
                                                 bool count_iteration) {
   if (count_iteration) st->iters += 1;
@@ -106,13 +109,16 @@ __device__ __forceinline__ void finish_residual(CgState* st, const double (&tot)
 
 // residual sums of the initial residual
 template <typename T>
-__global__ void __launch_bounds__(kRedThreads)
-k_cg_init2(const T* __restrict__ r, const double* __restrict__ D, long long N, CgState* st,
-           double* red) {
-  if (st->done) return;
+__global__ void __launch_bounds__(kRedThreads) k_cg_init2(const ImgDev* __restrict__ imgs) {
+  const ImgDev& im = imgs[blockIdx.y];
+  CgState* st = im.st;
+  if (st->done || blockIdx.x >= (unsigned)im.nred) return;
+  const T* r = reinterpret_cast<const T*>(im.vec[V_R]);
+  const double* D = im.D;
+  const long long N = im.N;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < N;
-       i += (long long)gridDim.x * kRedThreads) {
+       i += (long long)im.nred * kRedThreads) {
     const double rv = (double)r[i];
     const double t = rv * pinv<T>(st, D, i);
     s[0] += rv * rv;
@@ -121,20 +127,26 @@ k_cg_init2(const T* __restrict__ r, const double* __restrict__ D, long long N, C
     s[3] += rv;
   }
   double tot[4];
-  if (!grid_reduce<4>(s, red, &st->ticket[2], tot)) return;
+  if (!grid_reduce<4>(s, im.red, &st->ticket[2], tot, im.nred)) return;
   if (threadIdx.x == 0) finish_residual(st, tot, N, false);
 }
 
 // z += a p, r -= a Pi q, then the residual sums
 template <typename T>
-__global__ void __launch_bounds__(kRedThreads)
-k_cg_update(T* __restrict__ z, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
-            const double* __restrict__ D, long long N, CgState* st, double* red) {
-  if (st->done) return;
+__global__ void __launch_bounds__(kRedThreads) k_cg_update(const ImgDev* __restrict__ imgs) {
+  const ImgDev& im = imgs[blockIdx.y];
+  CgState* st = im.st;
+  if (st->done || blockIdx.x >= (unsigned)im.nred) return;
+  T* __restrict__ z = reinterpret_cast<T*>(im.vec[V_Z]);
+  T* __restrict__ r = reinterpret_cast<T*>(im.vec[V_R]);
+  const T* __restrict__ p = reinterpret_cast<const T*>(im.vec[V_P]);
+  const T* __restrict__ q = reinterpret_cast<const T*>(im.vec[V_Q]);
+  const double* D = im.D;
+  const long long N = im.N;
   const double a = st->a, mq = st->mean_q;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < N;
-       i += (long long)gridDim.x * kRedThreads) {
+       i += (long long)im.nred * kRedThreads) {
     z[i] = (T)((double)z[i] + a * (double)p[i]);
     const T rt = (T)((double)r[i] - a * ((double)q[i] - mq));
     r[i] = rt;
@@ -146,17 +158,21 @@ k_cg_update(T* __restrict__ z, T* __restrict__ r, const T* __restrict__ p, const
     s[3] += rv;
   }
   double tot[4];
-  if (!grid_reduce<4>(s, red, &st->ticket[3], tot)) return;
+  if (!grid_reduce<4>(s, im.red, &st->ticket[3], tot, im.nred)) return;
   if (threadIdx.x == 0) finish_residual(st, tot, N, true);
 }
 
 // r <- r - mean(r) (stored residual back into the complement of 1), p <- Pi(r / P) + beta p
 template <typename T>
-__global__ void k_cg_direction(T* __restrict__ r, T* __restrict__ p, const double* __restrict__ D,
-                               long long N, const CgState* __restrict__ st, int first) {
+__global__ void k_cg_direction(const ImgDev* __restrict__ imgs, int first) {
+  const ImgDev& im = imgs[blockIdx.y];
+  const CgState* st = im.st;
   if (st->done) return;
+  T* __restrict__ r = reinterpret_cast<T*>(im.vec[V_R]);
+  T* __restrict__ p = reinterpret_cast<T*>(im.vec[V_P]);
+  const double* D = im.D;
   const double mt = st->mean_t, beta = st->beta, c = st->mean_r;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < im.N;
        i += (long long)gridDim.x * blockDim.x) {
     const double rv = (double)r[i] - c;
     r[i] = (T)rv;
@@ -166,11 +182,15 @@ __global__ void k_cg_direction(T* __restrict__ r, T* __restrict__ p, const doubl
 }
 
 template <typename T>
-__global__ void k_cg_finish(const T* __restrict__ z, const T* __restrict__ f, T* __restrict__ u,
-                            long long N, const CgState* __restrict__ st) {
+__global__ void k_cg_finish(const ImgDev* __restrict__ imgs) {
+  const ImgDev& im = imgs[blockIdx.y];
+  const CgState* st = im.st;
+  const T* z = reinterpret_cast<const T*>(im.vec[V_Z]);
+  const T* f = reinterpret_cast<const T*>(im.vec[V_F]);
+  T* u = reinterpret_cast<T*>(im.vec[V_U]);
   const bool constant = st->const_f == 0.0 && st->deflate;
   const double mf = st->mean_f;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < im.N;
        i += (long long)gridDim.x * blockDim.x)
     u[i] = constant ? f[i] : (T)(mf + (double)z[i]);
 }
@@ -186,6 +206,21 @@ __global__ void k_max(const double* __restrict__ x, long long N, double* __restr
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = sh[0];
+}
+
+// max of every image's degree vector, one block per image
+__global__ void k_max_imgs(const ImgDev* __restrict__ imgs, double* __restrict__ out) {
+  const ImgDev& im = imgs[blockIdx.x];
+  __shared__ double sh[1024];
+  double m = -INFINITY;
+  for (long long i = threadIdx.x; i < im.N; i += 1024) m = fmax(m, im.D[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
 }
 
 inline unsigned grid_for(long long n, int threads = 256) {
@@ -210,17 +245,19 @@ nld_status run_pcg_t(Plan& P, double alpha, const void* f, void* u, const nld_pc
   h->deflate = o.deflate;
   h->status = NLD_OK;
   NLD_HIP(hipMemcpyAsync(P.st, h, sizeof(CgState), hipMemcpyHostToDevice, s));
-  const T* u0 = (const T*)(o.use_u0 ? u : f);
-  const unsigned rb = red_blocks(N);
-  const unsigned gb = grid_for(N);
-  hipLaunchKernelGGL(k_cg_stats<T>, dim3(rb), dim3(kRedThreads), 0, s, (const T*)f, u0, P.D, N, P.st,
-                     P.red);
-  hipLaunchKernelGGL(k_cg_z0<T>, dim3(gb), dim3(256), 0, s, u0, (T*)P.z, N, P.st);
+  P.img_host->vec[V_F] = const_cast<void*>(f);
+  P.img_host->vec[V_U] = u;
+  NLD_HIP(hipMemcpyAsync(P.d_img, P.img_host, sizeof(ImgDev), hipMemcpyHostToDevice, s));
+  const int u0sel = o.use_u0 ? V_U : V_F;
+  const dim3 rb(P.ls.max_nred, 1);
+  const dim3 gb(grid_for(N), 1);
+  const ImgDev* im = P.d_img;
+  hipLaunchKernelGGL(k_cg_stats<T>, rb, dim3(kRedThreads), 0, s, im, u0sel);
+  hipLaunchKernelGGL(k_cg_z0<T>, gb, dim3(256), 0, s, im, u0sel);
   NLD_HIP(hipGetLastError());
-  matvec(P, P.z, P.r, EPI_CG_INIT, f, s);
-  hipLaunchKernelGGL(k_cg_init2<T>, dim3(rb), dim3(kRedThreads), 0, s, (const T*)P.r, P.D, N, P.st,
-                     P.red);
-  hipLaunchKernelGGL(k_cg_direction<T>, dim3(gb), dim3(256), 0, s, (T*)P.r, (T*)P.p, P.D, N, P.st, 1);
+  matvec(P, nullptr, nullptr, EPI_CG_INIT, s);
+  hipLaunchKernelGGL(k_cg_init2<T>, rb, dim3(kRedThreads), 0, s, im);
+  hipLaunchKernelGGL(k_cg_direction<T>, gb, dim3(256), 0, s, im, 1);
   NLD_HIP(hipGetLastError());
   const bool trace = std::getenv("NLD_TRACE_CG") != nullptr;
   const int chunk = trace ? 1 : 4;
@@ -244,23 +281,20 @@ nld_status run_pcg_t(Plan& P, double alpha, const void* f, void* u, const nld_pc
     if (h->done || launched >= o.maxit) break;
     for (int k = 0; k < chunk; ++k) {
       if (o.timing) NLD_HIP(hipEventRecord(new_event(), s));
-      matvec(P, P.p, P.q, EPI_CG_Q, nullptr, s);
+      matvec(P, nullptr, nullptr, EPI_CG_Q, s);
       if (o.timing) NLD_HIP(hipEventRecord(new_event(), s));
-      hipLaunchKernelGGL(k_cg_update<T>, dim3(rb), dim3(kRedThreads), 0, s, (T*)P.z, (T*)P.r,
-                         (const T*)P.p, (const T*)P.q, P.D, N, P.st, P.red);
-      hipLaunchKernelGGL(k_cg_direction<T>, dim3(gb), dim3(256), 0, s, (T*)P.r, (T*)P.p, P.D, N,
-                         P.st, 0);
+      hipLaunchKernelGGL(k_cg_update<T>, rb, dim3(kRedThreads), 0, s, im);
+      hipLaunchKernelGGL(k_cg_direction<T>, gb, dim3(256), 0, s, im, 0);
       NLD_HIP(hipGetLastError());
       ++launched;
     }
   }
-  hipLaunchKernelGGL(k_cg_finish<T>, dim3(gb), dim3(256), 0, s, (const T*)P.z, (const T*)f, (T*)u, N,
-                     P.st);
+  hipLaunchKernelGGL(k_cg_finish<T>, gb, dim3(256), 0, s, im);
   NLD_HIP(hipGetLastError());
   double rr_true = -1.0;
   if (o.true_residual && !(h->const_f == 0.0 && o.deflate)) {
     // true residual of the final iterate: || Pi (f_perp - A z) ||
-    matvec(P, P.z, nullptr, EPI_CG_TRUE, f, s);
+    matvec(P, nullptr, nullptr, EPI_CG_TRUE, s);
   }
   NLD_HIP(hipMemcpyAsync(h, P.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
   NLD_HIP(hipStreamSynchronize(s));
@@ -353,12 +387,287 @@ nld_status run_adjoint(Plan& P, double alpha, const void* u, const void* g, void
 nld_status run_pcg(Plan& P, double alpha, const void* f, void* u, const nld_pcg_opts& o,
                    nld_pcg_info& info, hipStream_t s) {
   if (!P.have_D) {
-    matvec(P, P.ones, P.D, EPI_DEGREE, nullptr, s);
+    matvec(P, P.ones, P.D, EPI_DEGREE, s);
     P.have_D = true;
     compute_max_eta(P, s);
   }
   if (P.prec == NLD_FP32) return run_pcg_t<float>(P, alpha, f, u, o, info, s);
   return run_pcg_t<double>(P, alpha, f, u, o, info, s);
+}
+
+// ---------------------------------------------------------------------------- batched solves
+// Independent solves of several plans advance together: the window tables, schedules and image
+// tables of the plans are concatenated, so every stage of an iteration (spreading, fold, the
+// convolution passes, gathering, the epilogue and the CG updates) is one launch for the whole
+// batch, and a finished solve only costs the early exit of its workgroups.  Each image keeps
+// its own reduction blocks, so its iterates are bit-identical to a solve of its plan alone.
+// A chunk of iterations is captured once as a HIP graph and replayed until every solve has
+// finished (polled on the host between chunks).
+
+namespace {
+
+template <typename X>
+X* dev_copy(const std::vector<X>& h, hipStream_t s, std::vector<void*>& owned) {
+  X* d = nullptr;
+  NLD_HIP(hipMallocAsync((void**)&d, std::max<size_t>(1, h.size()) * sizeof(X), s));
+  owned.push_back(d);
+  if (!h.empty()) NLD_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice, s));
+  return d;
+}
+
+hipStream_t batch_stream() {
+  // one non-blocking stream (default priority) per device for the captured iteration chunks
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  NLD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw std::runtime_error("device index out of range");
+  if (!streams[dev]) NLD_HIP(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+  return streams[dev];
+}
+
+template <typename T>
+nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void* const* f,
+                             void* const* u, int count, const nld_pcg_opts& o, nld_pcg_info* infos,
+                             hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t cs = batch_stream();
+  hipEvent_t ev_in, ev_out;
+  NLD_HIP(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+  NLD_HIP(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+  NLD_HIP(hipEventRecord(ev_in, s));
+  NLD_HIP(hipStreamWaitEvent(cs, ev_in, 0));
+  std::vector<void*> owned;
+  CgState* sth = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto cleanup = [&]() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void* b : owned) (void)hipFreeAsync(b, cs);
+    (void)hipStreamSynchronize(cs);
+    if (sth) (void)hipHostFree(sth);
+    (void)hipEventDestroy(ev_in);
+    (void)hipEventDestroy(ev_out);
+  };
+  try {
+    // ---- concatenated tables
+    std::vector<WinDev> wins;
+    std::vector<TileJob> tj[3];
+    std::vector<Fold3Job> f3[2];
+    std::vector<FoldJob> fj;
+    std::vector<ConvJob> cj[3][4];
+    std::vector<ImgDev> imgs(count);
+    LaunchSet ls;
+    ls.prec = plans[0]->prec;
+    ls.m = plans[0]->wins[0].m;
+    ls.n_imgs = count;
+    CgState* d_st = nullptr;
+    NLD_HIP(hipMallocAsync((void**)&d_st, (size_t)count * sizeof(CgState), cs));
+    owned.push_back(d_st);
+    double* d_red = nullptr;
+    NLD_HIP(hipMallocAsync((void**)&d_red, (size_t)count * kRedBlocks * 8 * sizeof(double), cs));
+    owned.push_back(d_red);
+    for (int b = 0; b < count; ++b) {
+      Plan& P = *plans[b];
+      const int wo = (int)wins.size();
+      for (const WinDev& w0 : P.wins) {
+        WinDev w = w0;
+        w.img = b;
+        wins.push_back(w);
+      }
+      for (int g = 0; g < 3; ++g)
+        for (int j = P.tjob_begin[g]; j < P.tjob_begin[g + 1]; ++j) {
+          TileJob t = P.h_tjobs[j];
+          t.win += wo;
+          tj[g].push_back(t);
+        }
+      for (Fold3Job j : P.h_f3jobs) {
+        j.win += wo;
+        f3[P.f3_ts == 16 ? 1 : 0].push_back(j);
+      }
+      for (FoldJob j : P.h_fjobs) {
+        j.win += wo;
+        fj.push_back(j);
+      }
+      for (int ax = 0; ax < 3; ++ax)
+        for (int gi = 0; gi < 4; ++gi)
+          for (int j = P.conv_begin[ax][gi]; j < P.conv_begin[ax][gi + 1]; ++j) {
+            ConvJob c = P.h_conv[ax][j];
+            c.win += wo;
+            cj[ax][gi].push_back(c);
+          }
+      ImgDev& im = imgs[b];
+      im = *P.img_host;
+      im.win0 = wo;
+      im.vec[V_F] = const_cast<void*>(f[b]);
+      im.vec[V_U] = u[b];
+      im.st = d_st + b;
+      im.red = d_red + (size_t)b * kRedBlocks * 8;
+      ls.max_padded = std::max(ls.max_padded, P.max_padded);
+      ls.max_N = std::max<long long>(ls.max_N, P.N);
+      ls.max_nred = std::max(ls.max_nred, im.nred);
+      ls.has_flat = ls.has_flat || P.has_flat;
+    }
+    std::vector<TileJob> tjobs;
+    for (int g = 0; g < 3; ++g) {
+      // largest chunks first, across the whole batch
+      std::stable_sort(tj[g].begin(), tj[g].end(), [](const TileJob& a, const TileJob& b) {
+        return (a.pend - a.pbeg) > (b.pend - b.pbeg);
+      });
+      ls.tjob_begin[g] = (int)tjobs.size();
+      tjobs.insert(tjobs.end(), tj[g].begin(), tj[g].end());
+    }
+    ls.tjob_begin[3] = (int)tjobs.size();
+    std::vector<Fold3Job> f3all(f3[0]);
+    f3all.insert(f3all.end(), f3[1].begin(), f3[1].end());
+    ls.f3_begin[0] = 0;
+    ls.f3_begin[1] = (int)f3[0].size();
+    ls.f3_begin[2] = (int)f3all.size();
+    ls.n_fjobs = (int)fj.size();
+    ls.d_wins = dev_copy(wins, cs, owned);
+    ls.d_tjobs = dev_copy(tjobs, cs, owned);
+    ls.d_f3jobs = dev_copy(f3all, cs, owned);
+    ls.d_fjobs = dev_copy(fj, cs, owned);
+    for (int ax = 0; ax < 3; ++ax) {
+      std::vector<ConvJob> all;
+      for (int gi = 0; gi < 4; ++gi) {
+        ls.conv_begin[ax][gi] = (int)all.size();
+        all.insert(all.end(), cj[ax][gi].begin(), cj[ax][gi].end());
+      }
+      ls.conv_begin[ax][4] = (int)all.size();
+      ls.d_conv[ax] = dev_copy(all, cs, owned);
+    }
+    ls.d_imgs = dev_copy(imgs, cs, owned);
+
+    // ---- degree vectors (every image, if any plan still lacks its own) and max eta
+    bool need_D = false;
+    for (int b = 0; b < count; ++b) need_D = need_D || !plans[b]->have_D;
+    NLD_HIP(hipHostMalloc((void**)&sth, (size_t)count * sizeof(CgState), hipHostMallocDefault));
+    if (need_D) {
+      matvec_set(ls, VecArg{nullptr, V_ONES}, VecArg{nullptr, V_Q}, nullptr, EPI_DEGREE, cs);
+      double* d_max = nullptr;
+      NLD_HIP(hipMallocAsync((void**)&d_max, (size_t)count * sizeof(double), cs));
+      owned.push_back(d_max);
+      hipLaunchKernelGGL(k_max_imgs, dim3(count), dim3(1024), 0, cs, ls.d_imgs, d_max);
+      NLD_HIP(hipGetLastError());
+      std::vector<double> mx(count);
+      NLD_HIP(hipMemcpyAsync(mx.data(), d_max, count * sizeof(double), hipMemcpyDeviceToHost, cs));
+      NLD_HIP(hipStreamSynchronize(cs));
+      for (int b = 0; b < count; ++b) {
+        double wsum = 0.0;
+        for (double w : plans[b]->weight) wsum += w;
+        plans[b]->max_eta = mx[b] - wsum;
+        plans[b]->have_D = true;
+      }
+    }
+
+    // ---- CG set-up
+    for (int b = 0; b < count; ++b) {
+      double wsum = 0.0;
+      for (double w : plans[b]->weight) wsum += w;
+      CgState& h = sth[b];
+      h = CgState{};
+      h.alpha = alpha[b];
+      h.tol = o.tol;
+      h.wsum = wsum;
+      h.maxit = o.maxit;
+      h.precond = o.precond;
+      h.deflate = o.deflate;
+      h.status = NLD_OK;
+    }
+    NLD_HIP(hipMemcpyAsync(d_st, sth, (size_t)count * sizeof(CgState), hipMemcpyHostToDevice, cs));
+    const int u0sel = o.use_u0 ? V_U : V_F;
+    const dim3 rb(ls.max_nred, count);
+    const dim3 gb(grid_for(ls.max_N), count);
+    const ImgDev* dimg = ls.d_imgs;
+    hipLaunchKernelGGL(k_cg_stats<T>, rb, dim3(kRedThreads), 0, cs, dimg, u0sel);
+    hipLaunchKernelGGL(k_cg_z0<T>, gb, dim3(256), 0, cs, dimg, u0sel);
+    NLD_HIP(hipGetLastError());
+    matvec_set(ls, VecArg{nullptr, V_Z}, VecArg{nullptr, V_R}, nullptr, EPI_CG_INIT, cs);
+    hipLaunchKernelGGL(k_cg_init2<T>, rb, dim3(kRedThreads), 0, cs, dimg);
+    hipLaunchKernelGGL(k_cg_direction<T>, gb, dim3(256), 0, cs, dimg, 1);
+    NLD_HIP(hipGetLastError());
+
+    // ---- iterations: chunks of 4, captured once as a graph
+    const int chunk = 4;
+    auto body = [&]() {
+      for (int k = 0; k < chunk; ++k) {
+        matvec_set(ls, VecArg{nullptr, V_P}, VecArg{nullptr, V_Q}, nullptr, EPI_CG_Q, cs);
+        hipLaunchKernelGGL(k_cg_update<T>, rb, dim3(kRedThreads), 0, cs, dimg);
+        hipLaunchKernelGGL(k_cg_direction<T>, gb, dim3(256), 0, cs, dimg, 0);
+        NLD_HIP(hipGetLastError());
+      }
+    };
+    const bool use_graph = std::getenv("NLD_NO_GRAPH") == nullptr;
+    std::vector<double> done_ms(count, -1.0);
+    int launched = 0;
+    bool captured = false;
+    while (true) {
+      NLD_HIP(hipMemcpyAsync(sth, d_st, (size_t)count * sizeof(CgState), hipMemcpyDeviceToHost, cs));
+      NLD_HIP(hipStreamSynchronize(cs));
+      const double now = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      int open = 0;
+      for (int b = 0; b < count; ++b) {
+        if (sth[b].done && done_ms[b] < 0) done_ms[b] = now;
+        open += !sth[b].done;
+      }
+      if (open == 0 || launched >= o.maxit) break;
+      if (use_graph && launched > 0 && !captured) {
+        // the first chunk ran eagerly (kernel attributes are set); capture the next one
+        captured = true;
+        NLD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        body();
+        NLD_HIP(hipStreamEndCapture(cs, &graph));
+        NLD_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+      }
+      if (exec) NLD_HIP(hipGraphLaunch(exec, cs));
+      else body();
+      launched += chunk;
+    }
+
+    // ---- solutions, true residuals, reports
+    hipLaunchKernelGGL(k_cg_finish<T>, gb, dim3(256), 0, cs, dimg);
+    NLD_HIP(hipGetLastError());
+    if (o.true_residual) matvec_set(ls, VecArg{nullptr, V_Z}, VecArg{nullptr, V_R}, nullptr, EPI_CG_TRUE, cs);
+    NLD_HIP(hipMemcpyAsync(sth, d_st, (size_t)count * sizeof(CgState), hipMemcpyDeviceToHost, cs));
+    NLD_HIP(hipStreamSynchronize(cs));
+    const double end_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    nld_status worst = NLD_OK;
+    for (int b = 0; b < count; ++b) {
+      const CgState& h = sth[b];
+      nld_pcg_info& info = infos[b];
+      const bool cst = h.const_f == 0.0 && o.deflate;
+      info.iters = h.iters;
+      const double b2 = h.bnorm2;
+      info.relres_rec = cst ? 0.0 : (b2 > 0 ? std::sqrt(h.rr / b2) : 0.0);
+      info.relres_true = (o.true_residual && !cst) ? (b2 > 0 ? std::sqrt(std::max(h.rr_true, 0.0) / b2) : 0.0) : -1.0;
+      info.kappa_est = 2.0 * alpha[b] * plans[b]->max_eta + 1.0;
+      info.ms_solve = done_ms[b] >= 0 ? done_ms[b] : end_ms;
+      info.ms_matvec = 0.0;
+      info.matvecs_timed = 0;
+      nld_status stt = (nld_status)h.status;
+      if (stt == NLD_OK && !h.done) stt = NLD_E_NOCONV;
+      info.status = stt;
+      if (stt != NLD_OK && worst == NLD_OK) worst = stt;
+    }
+    NLD_HIP(hipEventRecord(ev_out, cs));
+    NLD_HIP(hipStreamWaitEvent(s, ev_out, 0));
+    cleanup();
+    return worst;
+  } catch (...) {
+    (void)hipStreamEndCapture(cs, &graph);
+    cleanup();
+    throw;
+  }
+}
+
+}  // namespace
+
+nld_status run_pcg_batched(Plan* const* plans, const double* alpha, const void* const* f,
+                           void* const* u, int count, const nld_pcg_opts& o, nld_pcg_info* infos,
+                           hipStream_t s) {
+  if (plans[0]->prec == NLD_FP32) return run_pcg_batched_t<float>(plans, alpha, f, u, count, o, infos, s);
+  return run_pcg_batched_t<double>(plans, alpha, f, u, count, o, infos, s);
 }
 
 }  // namespace nld

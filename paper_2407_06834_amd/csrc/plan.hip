@@ -625,8 +625,9 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
       // the spreading accumulates the padded tile in FP64
       // 8^3 tiles: smaller padded tiles in LDS give more resident workgroups, which measured
       // faster than 16^3 tiles on the 512^2 workload despite the larger halo overhead
-      tsz = 8;
-      if (const char* e = std::getenv("NLD_TILE3")) tsz = std::atoi(e);
+      tsz = P.tile3 ? P.tile3 : 8;
+      if (P.tile3 == 0)
+        if (const char* e = std::getenv("NLD_TILE3")) tsz = std::atoi(e);
       if (tsz != 8 && tsz != 16) tsz = 8;
       if ((long long)std::pow(tsz + 2 * m - 1, 3) * 8LL > P.lds_limit) tsz = 8;
     } else if (t == 2) {
@@ -760,6 +761,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
                  "max_padded=%lld psi_err=%.2e\n", (long long)N, L, tile_total, ne, jobs.size(), slots,
                  maxc, max_padded, P.psi_err);
   }
+  P.h_tjobs = jobs;
   P.d_tjobs = dalloc<TileJob>(std::max<size_t>(1, jobs.size()), s);
   NLD_HIP(hipMemcpyAsync(P.d_tjobs, jobs.data(), jobs.size() * sizeof(TileJob), hipMemcpyHostToDevice, s));
   P.n_tiles_total = (int)tile_total;
@@ -787,6 +789,8 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
         fj.push_back(FoldJob{l, (int)std::min<long long>(256, w.grid_size - c), c});
     }
   }
+  P.h_fjobs = fj;
+  P.h_f3jobs = f3;
   P.n_fjobs = (int)fj.size();
   P.d_fjobs = dalloc<FoldJob>(std::max<size_t>(1, fj.size()), s);
   NLD_HIP(hipMemcpyAsync(P.d_fjobs, fj.data(), fj.size() * sizeof(FoldJob), hipMemcpyHostToDevice, s));
@@ -824,6 +828,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
       }
     }
     P.conv_begin[ax][4] = (int)cjobs.size();
+    P.h_conv[ax] = cjobs;
     if (!cjobs.empty()) {
       P.d_conv[ax] = dalloc<ConvJob>(cjobs.size(), s);
       NLD_HIP(hipMemcpyAsync(P.d_conv[ax], cjobs.data(), cjobs.size() * sizeof(ConvJob),
@@ -851,8 +856,70 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   hipLaunchKernelGGL(k_fill<unsigned char>, dim3(1), dim3(256), 0, s, (unsigned char*)P.st,
                      (long long)sizeof(CgState), (unsigned char)0);
   NLD_HIP(hipGetLastError());
+  // every window points at the plan's buffers
+  for (int l = 0; l < L; ++l) {
+    WinDev& w = P.wins[l];
+    w.img = 0;
+    w.wl = l;
+    w.N = N;
+    w.LN = LN;
+    w.g_idx = P.g_idx;
+    w.g_base = P.g_base;
+    w.g_frac = P.g_frac;
+    w.grid = P.grid;
+    w.padded = P.padded;
+    w.slot_stride = P.slot_stride;
+    w.tile_slot0 = P.tile_slot0;
+    w.tile_nslot = P.tile_nslot;
+    w.ylocal = static_cast<T*>(P.ylocal) + (long long)l * N;
+  }
   std::vector<WinDev> wins_dv[3];
   upload_windows<T>(P, wins_dv, s);
+  // the plan's own image table (f and u are set by each solve)
+  const int nred = (int)std::max<long long>(1, std::min<long long>(kRedBlocks, (N + kRedThreads - 1) / kRedThreads));
+  NLD_HIP(hipHostMalloc((void**)&P.img_host, sizeof(ImgDev), hipHostMallocDefault));
+  ImgDev& im = *P.img_host;
+  im = ImgDev{};
+  im.N = N;
+  im.win0 = 0;
+  im.L = L;
+  im.nred = nred;
+  im.vec[V_Z] = P.z;
+  im.vec[V_R] = P.r;
+  im.vec[V_P] = P.p;
+  im.vec[V_Q] = P.q;
+  im.vec[V_F] = nullptr;
+  im.vec[V_U] = nullptr;
+  im.vec[V_ONES] = P.ones;
+  im.D = P.D;
+  im.sumv = P.sumv;
+  im.st = P.st;
+  im.red = P.red;
+  P.d_img = dalloc<ImgDev>(1, s);
+  NLD_HIP(hipMemcpyAsync(P.d_img, P.img_host, sizeof(ImgDev), hipMemcpyHostToDevice, s));
+  LaunchSet& ls = P.ls;
+  ls = LaunchSet{};
+  ls.prec = P.prec;
+  ls.m = P.wins[0].m;
+  ls.d_wins = P.d_wins;
+  ls.d_tjobs = P.d_tjobs;
+  for (int g = 0; g < 4; ++g) ls.tjob_begin[g] = P.tjob_begin[g];
+  ls.max_padded = P.max_padded;
+  ls.d_f3jobs = P.d_f3jobs;
+  ls.f3_begin[0] = 0;
+  ls.f3_begin[1] = (P.f3_ts == 16) ? 0 : P.n_f3jobs;
+  ls.f3_begin[2] = P.n_f3jobs;
+  ls.d_fjobs = P.d_fjobs;
+  ls.n_fjobs = P.n_fjobs;
+  for (int ax = 0; ax < 3; ++ax) {
+    ls.d_conv[ax] = P.d_conv[ax];
+    for (int g = 0; g < 5; ++g) ls.conv_begin[ax][g] = P.conv_begin[ax][g];
+  }
+  ls.d_imgs = P.d_img;
+  ls.n_imgs = 1;
+  ls.max_N = N;
+  ls.max_nred = nred;
+  ls.has_flat = P.has_flat;
 
   dfree(d_cp, s);
   dfree(base, s);
@@ -936,9 +1003,11 @@ void release_plan(Plan& P) {
                   P.tile_nslot, P.ylocal, P.D, P.sumv, P.ones, P.psi, P.d_tjobs, P.d_fjobs, P.d_f3jobs, P.d_conv[0], P.d_conv[1],
                   P.d_conv[2], P.z, P.r, P.p, P.q, P.red, P.st, P.coef_dv, P.d_wins_dv[0],
                   P.d_wins_dv[1], P.d_wins_dv[2], P.grid_save, P.yk, P.yks, P.dl, P.dls,
-                  P.adj_part};
+                  P.adj_part, P.d_img};
   for (void* b : bufs) dfree(b, s);
   (void)hipStreamSynchronize(s);
+  if (P.img_host) (void)hipHostFree(P.img_host);
+  P.img_host = nullptr;
 }
 
 }  // namespace nld

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NOCONV", 
 
 # Entry points declared in include/nld.h
 SYMBOLS = ("nfft_plan", "nfft_plan_update_kernel", "nfft_plan_destroy", "nfft_plan_window_info", "nfft_plan_size",
-           "degree_vector", "anova_matvec", "laplacian_matvec", "pcg_solve", "adjoint_solve",
+           "degree_vector", "anova_matvec", "laplacian_matvec", "pcg_solve", "pcg_solve_batched", "adjoint_solve",
            "features_from_image", "nld_last_error")
 
 
@@ -88,6 +88,8 @@ def load() -> ctypes.CDLL:
         "anova_matvec": [P, P, P, P],
         "laplacian_matvec": [P, P, P, P],
         "pcg_solve": [P, D, P, P, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo), P],
+        "pcg_solve_batched": [ctypes.POINTER(P), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(P),
+                              ctypes.POINTER(P), I32, ctypes.POINTER(PcgOpts), ctypes.POINTER(PcgInfo), P],
         "adjoint_solve": [P, D, P, P, P, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(PcgOpts),
                           ctypes.POINTER(PcgInfo), P],
         "features_from_image": [P, I32, I32, I32, I32, I32, P, P],
@@ -308,6 +310,29 @@ def window_table(rho: int, with_pos: bool = True):
     wins = [[0, 1, centre]] if with_pos else []
     wins += [rest[s:s + 3] for s in range(0, len(rest), 3)]
     return wins
+
+
+def pcg_solve_batched(plans, alphas, fs, us=None, tol: float = 1e-6, maxit: int = 500,
+                      precond: bool = True, deflate: bool = True, use_u0: bool = False,
+                      true_residual: bool = False, stream=None):
+    """Solves (I + alpha_b L_b) u_b = f_b for every plan b together (see pcg_solve_batched in
+    nld.h).  Returns (list of u_b, list of info dicts, status)."""
+    n = len(plans)
+    if not (len(alphas) == len(fs) == n) or n == 0:
+        raise ValueError("plans, alphas and fs must have the same nonzero length")
+    if us is None:
+        us = [torch.empty_like(f) for f in fs]
+    ph = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    al = (ctypes.c_double * n)(*[float(a) for a in alphas])
+    fp = (ctypes.c_void_p * n)(*[_vec(f, p.N, p.dtype, "f").value for f, p in zip(fs, plans)])
+    up = (ctypes.c_void_p * n)(*[_vec(u, p.N, p.dtype, "u").value for u, p in zip(us, plans)])
+    opts = PcgOpts(float(tol), int(maxit), int(use_u0), int(precond), int(deflate),
+                   int(true_residual), 0)
+    infos = (PcgInfo * n)()
+    st = load().pcg_solve_batched(ph, al, fp, up, n, ctypes.byref(opts), infos, _stream(stream))
+    if st not in (NLD_OK, NLD_E_NOCONV, NLD_E_BREAKDOWN):
+        _check(st)
+    return us, [infos[b].as_dict() for b in range(n)], st
 
 
 def adjoint_solve(plan: Plan, alpha, f, u, g, **kw):

@@ -1,0 +1,83 @@
+"""GPU tests of the batched solves: every solve of a batch equals the solve of its plan alone,
+bit for bit, with and without the captured iteration graph."""
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import torch_gpu
+from paper_2407_06834_amd.synth import make_image
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(32, 32), (48, 40), (64, 64), (17, 23), (80, 56)]
+
+
+def _problems(torch, nld, dtype, sizes=SIZES, seed=300):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, (n1, n2) in enumerate(sizes):
+        _, f = make_image(seed + k, n1, n2, 3, 2, 0.1)
+        img = torch.tensor(f, dtype=dtype, device="cuda")
+        F = nld.features_from_image(img, 1)
+        sig = list(rng.uniform(0.08, 0.2, 4))
+        alpha = float(np.exp(rng.uniform(np.log(0.05), np.log(20.0))))
+        m = 4 if dtype == torch.float32 else 8
+        plan = nld.Plan(F, nld.window_table(1), sig, [1.0] * 4, bandwidth=64, cutoff=m)
+        out.append((plan, alpha, img.reshape(-1).contiguous()))
+    return out
+
+
+@pytest.mark.parametrize("dtype_name", ["float64", "float32"])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batched_equals_single_solves(dtype_name, graph):
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    dtype = getattr(torch, dtype_name)
+    tol = 1e-10 if dtype == torch.float64 else 1e-6
+    probs = _problems(torch, nld, dtype)
+    singles = [p.pcg_solve(a, f, tol=tol, maxit=500) for p, a, f in probs]
+    if not graph:
+        os.environ["NLD_NO_GRAPH"] = "1"
+    try:
+        us, infos, st = nld.pcg_solve_batched([p for p, _, _ in probs], [a for _, a, _ in probs],
+                                              [f for _, _, f in probs], tol=tol, maxit=500)
+    finally:
+        os.environ.pop("NLD_NO_GRAPH", None)
+    assert st == nld.NLD_OK
+    for (u1, i1), u, i in zip(singles, us, infos):
+        assert i["status"] == "OK" and i1["status"] == "OK"
+        assert i["iters"] == i1["iters"]
+        assert torch.equal(u, u1)
+    for p, _, _ in probs:
+        p.close()
+
+
+def test_batched_statuses_constant_image_and_iteration_limit():
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    probs = _problems(torch, nld, torch.float64, sizes=[(32, 32), (40, 40), (24, 24)], seed=320)
+    plans = [p for p, _, _ in probs]
+    fs = [f for _, _, f in probs]
+    fs[1] = torch.full_like(fs[1], 0.25)   # constant right-hand side: u = f, no iteration
+    alphas = [a for _, a, _ in probs]
+    us, infos, st = nld.pcg_solve_batched(plans, alphas, fs, tol=1e-12, maxit=3)
+    assert st == nld.NLD_E_NOCONV
+    assert infos[0]["status"] == "E_NOCONV" and infos[2]["status"] == "E_NOCONV"
+    assert infos[1]["status"] == "OK" and infos[1]["iters"] == 0
+    assert torch.equal(us[1], fs[1])
+    for p in plans:
+        p.close()
+
+
+def test_batched_rejects_duplicates_and_mixed_precision():
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    p64 = _problems(torch, nld, torch.float64, sizes=[(16, 16)], seed=330)[0]
+    p32 = _problems(torch, nld, torch.float32, sizes=[(16, 16)], seed=331)[0]
+    with pytest.raises(nld.NldError):
+        nld.pcg_solve_batched([p64[0], p64[0]], [1.0, 1.0], [p64[2], p64[2]])
+    with pytest.raises(nld.NldError):
+        nld.pcg_solve_batched([p64[0], p32[0]], [1.0, 1.0], [p64[2], p32[2]])
+    p64[0].close()
+    p32[0].close()
