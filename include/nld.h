@@ -63,6 +63,9 @@ typedef enum { NLD_FP32 = 0, NLD_FP64 = 1 } nld_prec;
  *   matvec_tol  target relative error of K_l v when M or m are selected automatically.
  *   prec        arithmetic of features, grids and vectors.  CG inner products, the
  *               deflation means, D and the Laplacian epilogue are FP64 in both modes.
+ *   tile        grid tile extent of 3-dimensional windows for the spreading and gathering
+ *               schedules: 8 or 16 (0 selects 8).  Results do not depend on it beyond
+ *               rounding; it trades halo work against workgroup count.
  */
 typedef struct {
   int32_t n_windows;
@@ -76,6 +79,7 @@ typedef struct {
   double oversampling;
   double matvec_tol;
   nld_prec prec;
+  int32_t tile;
 } nld_kernel_desc;
 
 /* Per-window parameters chosen by the plan (for reports and tests). */

@@ -100,6 +100,8 @@ nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t 
     return fail(NLD_E_INVAL, "nfft_plan: oversampling must be in [1.25, 8]");
   const double tol = desc->matvec_tol == 0.0 ? 1e-6 : desc->matvec_tol;
   if (!finite_pos(tol) || tol >= 1.0) return fail(NLD_E_INVAL, "nfft_plan: matvec_tol must be in (0, 1)");
+  if (desc->tile != 0 && desc->tile != 8 && desc->tile != 16)
+    return fail(NLD_E_INVAL, "nfft_plan: tile must be 0, 8 or 16");
   nld_plan_s* h = nullptr;
   nld_status st = guarded("nfft_plan", [&] {
     h = new nld_plan_s();
@@ -120,6 +122,7 @@ nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t 
     P.cutoff = desc->cutoff;
     P.oversampling = os;
     P.tol = tol;
+    P.tile3 = desc->tile;
     NLD_HIP(hipHostMalloc((void**)&P.st_host, sizeof(nld::CgState), hipHostMallocDefault));
     int dev = 0, lds = 65536;
     NLD_HIP(hipGetDevice(&dev));

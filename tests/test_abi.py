@@ -57,6 +57,7 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert plan(cutoff=9) == nld.NLD_E_INVAL
     assert plan(oversampling=1.0) == nld.NLD_E_INVAL
     assert plan(prec=7) == nld.NLD_E_INVAL
+    assert plan(tile=12) == nld.NLD_E_INVAL and "tile" in err()
     assert plan(n_windows=0) == nld.NLD_E_INVAL
     sg[0] = -1.0
     assert plan() == nld.NLD_E_INVAL and "sigma" in err()
@@ -75,3 +76,14 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert L.features_from_image(fake, 0, 4, 1, 1, 0, fake, None) == nld.NLD_E_INVAL
     assert L.features_from_image(fake, 4, 4, -1, 1, 0, fake, None) == nld.NLD_E_INVAL
     assert L.anova_matvec(None, fake, fake, None) == nld.NLD_E_INVAL
+    one = (ctypes.c_double * 1)(1.0)
+    ptrs = (ctypes.c_void_p * 1)(0x1000)
+    infos = (nld.PcgInfo * 1)()
+    assert L.pcg_solve_batched(ptrs, one, ptrs, ptrs, 0, ctypes.byref(opts), infos, None) == nld.NLD_E_INVAL
+    nulls = (ctypes.c_void_p * 1)(None)
+    assert L.pcg_solve_batched(nulls, one, ptrs, ptrs, 1, ctypes.byref(opts), infos, None) == nld.NLD_E_INVAL
+    assert "null" in err()
+    assert L.nfft_plan_update_kernel(None, one, one, None) == nld.NLD_E_INVAL
+    grad = (ctypes.c_double * 3)()
+    assert L.adjoint_solve(None, 1.0, fake, fake, fake, fake, grad, ctypes.byref(opts),
+                           ctypes.byref(info), None) == nld.NLD_E_INVAL

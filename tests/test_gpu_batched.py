@@ -81,3 +81,22 @@ def test_batched_rejects_duplicates_and_mixed_precision():
         nld.pcg_solve_batched([p64[0], p32[0]], [1.0, 1.0], [p64[2], p32[2]])
     p64[0].close()
     p32[0].close()
+
+
+def test_autotuner_picks_meet_the_error_target():
+    torch = torch_gpu()
+    from paper_2407_06834_amd import autotune
+    samples, counts = {}, {"64": 3, "96": 1}
+    for key, side in (("64", 64), ("96", 96)):
+        _, f = make_image(340 + side, side, side, 4, 3, 0.1)
+        samples[key] = (torch.tensor(f, dtype=torch.float32, device="cuda"), [0.12, 0.1, 0.15, 0.2],
+                        [1.0] * 4)
+    tuner, m, picks = autotune.tune_classes(samples, counts, dtype=torch.float32)
+    assert m in tuner.cutoffs()
+    for key, kw in picks.items():
+        assert kw["cutoff"] == m and kw["tile"] in (8, 16) and kw["oversampling"] in (2.0, 4.0)
+        chosen = [c for c in tuner.results[key] if (c.cutoff, c.oversampling, c.tile) ==
+                  (kw["cutoff"], kw["oversampling"], kw["tile"])]
+        assert len(chosen) == 1 and chosen[0].err <= tuner.matvec_tol
+        # the highest cutoff is far more accurate than the target (sanity of the measurement)
+        assert min(c.err for c in tuner.results[key] if c.cutoff == 5) < 1e-5
