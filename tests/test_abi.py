@@ -7,13 +7,13 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "nld.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("nld.h", "nld_cnn.h")]
 LIB = os.path.join(ROOT, "paper_2407_06834_amd", "libnld.so")
 
 
 def _declared():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:nld_status|const char\*)\s+(\w+)\s*\(", text, re.M)))
+    text = "".join(open(h).read() for h in HEADERS)
+    return sorted(set(re.findall(r"^(?:nld_status|const char\*|int64_t)\s+(\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -30,8 +30,10 @@ def test_every_declared_symbol_is_exported(lib):
             "degree_vector", "features_from_image", "nld_last_error"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
-    from paper_2407_06834_amd import nld
+    from paper_2407_06834_amd import cnn, nld
     assert set(nld.SYMBOLS) <= set(names)
+    assert set(cnn.SYMBOLS) <= set(names)
+    assert {"cnn_create", "cnn_predict", "cnn_loss_grad", "cnn_adam_step"} <= set(names)
 
 
 def test_invalid_arguments_rejected_on_host(lib):
@@ -87,3 +89,10 @@ def test_invalid_arguments_rejected_on_host(lib):
     grad = (ctypes.c_double * 3)()
     assert L.adjoint_solve(None, 1.0, fake, fake, fake, fake, grad, ctypes.byref(opts),
                            ctypes.byref(info), None) == nld.NLD_E_INVAL
+    from paper_2407_06834_amd import cnn
+    C = cnn._lib()
+    assert C.cnn_create(None, 2, 0) == nld.NLD_E_INVAL
+    hh = ctypes.c_void_p()
+    assert C.cnn_create(ctypes.byref(hh), 40, 0) == nld.NLD_E_INVAL and hh.value is None
+    assert C.cnn_param_count(None) == -1
+    assert C.cnn_predict(None, fake, fake, 1, 4, 4, fake, None) == nld.NLD_E_INVAL
