@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <type_traits>
 #include <stdexcept>
 
 #include "nld_device.h"
@@ -41,8 +43,14 @@ __device__ __forceinline__ int tile_origin(const WinDev& w, int tile, int dd) {
 
 
 // ---------------------------------------------------------------------------- window polynomial
-template <typename T, int K>
-__device__ __forceinline__ T horner(const T* c, T x) {
+// Pointers with an explicit address space: global (vector loads without the flat-address
+// check) and constant (uniform data the compiler may read with scalar loads).
+template <typename T> using GlobalPtr = const T __attribute__((address_space(1)))*;
+template <typename T> using ConstPtr = const T __attribute__((address_space(4)))*;
+template <typename T> using LdsPtr = const T __attribute__((address_space(3)))*;
+
+template <typename T, int K, typename P>
+__device__ __forceinline__ T horner(P c, T x) {
   T r = c[K - 1];
 #pragma unroll
   for (int k = K - 2; k >= 0; --k) r = r * x + c[k];
@@ -64,8 +72,8 @@ __device__ __forceinline__ double lane_bcast(double v, int q) {
 
 // Weights of the W = 2m taps of one node in one dimension (tap i at cell floor(u) - m + 1 + i,
 // distance fr + m - 1 - i): the per-tap window polynomials evaluated at x = 2 fr - 1.
-template <typename T, int W>
-__device__ __forceinline__ void poly_row(const T* psi, T fr, T* wt) {
+template <typename T, int W, typename P>
+__device__ __forceinline__ void poly_row(P psi, T fr, T* wt) {
   constexpr int K = PsiDeg<T>::value + 1;
   const T x = (T)2 * fr - (T)1;
 #pragma unroll
@@ -79,9 +87,10 @@ __device__ __forceinline__ void poly_row(const T* psi, T fr, T* wt) {
 // last two kept dimensions and keeps the 2m taps of the first kept dimension in registers, so a
 // run of r nodes costs one set of LDS additions instead of r.  When the cell changes the
 // registers are added into the padded tile (tile plus the 2m - 1 halo cells the taps reach) as
-// 64-bit fixed-point integers scaled by 2^(61 - e), 2^e <= sum |v| over the chunk: integer
-// addition is exact and associative, so the result does not depend on the order in which the
-// wavefronts add (reproducible), and ds_add_u64 is fast where LDS float atomics are not.
+// fixed-point integers scaled by 2^(29 - e) in 32 bits (FP32 data) or 2^(61 - e) in 64 bits (FP64
+// data), 2^e <= sum |v| over the chunk: integer addition is exact and associative, so the result
+// does not depend on the order in which the wavefronts add (reproducible), and ds_add_u32 /
+// ds_add_u64 are fast where LDS float atomics are not.
 // The slot is then written back in the working precision; the fold kernel sums the slots that
 // cover each grid cell.
 template <typename T, int W, int TD>
@@ -92,27 +101,33 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   const WinDev& w = wins[job.win];
   const ImgDev& im = imgs[w.img];
   if (check && im.st->done) return;
-  const T* __restrict__ v = vin<T>(im, in);
-  const int* __restrict__ g_idx = w.g_idx;
-  const unsigned* __restrict__ g_base = w.g_base;
-  const T* __restrict__ g_frac = reinterpret_cast<const T*>(w.g_frac);
+  GlobalPtr<T> v = (GlobalPtr<T>)vin<T>(im, in);
+  GlobalPtr<int> g_idx = (GlobalPtr<int>)w.g_idx;
+  GlobalPtr<unsigned> g_base = (GlobalPtr<unsigned>)w.g_base;
+  GlobalPtr<T> g_frac = (GlobalPtr<T>)w.g_frac;
   const long long LN = w.LN;
-  T* __restrict__ padded = reinterpret_cast<T*>(w.padded);
+  T __attribute__((address_space(1)))* padded = (T __attribute__((address_space(1)))*)w.padded;
   const long long slot_stride = w.slot_stride;
   constexpr int K = PsiDeg<T>::value + 1;
   constexpr int PAIRS = (TD == 1) ? W : W * W;
   constexpr int NP = (PAIRS + 63) / 64;
   constexpr int NI0 = (TD == 3) ? W : 1;
   constexpr bool REG = (NP * K * 2 * (int)sizeof(T) / 4) <= 72;
+  // fixed-point accumulators: 32-bit for FP32 data (resolution 2^-29 of the chunk's sum of
+  // |v|, far below FP32 rounding of the result), 64-bit for FP64 data (2^-61)
+  using Acc = typename std::conditional<sizeof(T) == 4, unsigned int, unsigned long long>::type;
+  using SAcc = typename std::conditional<sizeof(T) == 4, int, long long>::type;
+  constexpr int kFix = sizeof(T) == 4 ? 29 : 61;
   extern __shared__ unsigned char smem_raw[];
-  unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem_raw);
+  Acc* acc = reinterpret_cast<Acc*>(smem_raw);
   __shared__ double s_part[kSpreadWaves];
   __shared__ T s_psi[REG ? 1 : W * K];
   const int pe1 = w.pe[1], pe2 = w.pe[2];
   const int cells = w.pe[0] * pe1 * pe2;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const T* psi = reinterpret_cast<const T*>(w.psi);
-  for (int c = threadIdx.x; c < cells; c += kSpreadThreads) acc[c] = 0ull;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
+  GlobalPtr<T> psi = (GlobalPtr<T>)w.psi;
+  for (int c = threadIdx.x; c < cells; c += kSpreadThreads) acc[c] = (Acc)0;
   if constexpr (!REG)
     for (int c = threadIdx.x; c < W * K; c += kSpreadThreads) s_psi[c] = psi[c];
   // fixed-point scale of this chunk
@@ -124,12 +139,15 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   __syncthreads();
   double tot = 0.0;
   for (int k = 0; k < kSpreadWaves; ++k) tot += s_part[k];
-  T* out = padded + (long long)job.slot * slot_stride;
+  auto out = padded + (long long)job.slot * slot_stride;
   if (!(tot > 0.0)) {
     for (int c = threadIdx.x; c < cells; c += kSpreadThreads) out[c] = (T)0;
     return;
   }
-  const double scale = ldexp(1.0, 61 - ilogb(tot));
+  // |cell| <= sum |v| < 2^(e + 1): scaled values stay below 2^(kFix + 1)
+  const int e = max(ilogb(tot), -90);
+  const double scale = ldexp(1.0, kFix - e);
+  const T scale_t = (T)scale;
   // this lane's tap pairs and their window polynomials
   int i1[NP], i2[NP];
   bool pv[NP];
@@ -161,22 +179,32 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   for (int k = 0; k < NP; ++k)
 #pragma unroll
     for (int i = 0; i < NI0; ++i) accr[k][i] = (T)0;
+  // padded-tile offset of this lane's tap pair relative to a node's first tap, and the stride of
+  // the first dimension's taps
+  int loff[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) loff[k] = (TD >= 2 ? i1[k] * pe2 : 0) + i2[k];
+  const int s01 = pe1 * pe2;
   constexpr unsigned kNone = 0xffffffffu;
   unsigned cur = kNone;
+  // the register accumulators hold fixed-point units already (the node values are pre-scaled)
   auto flush = [&]() {
     const int l0 = (int)(cur & 255u) - o0, l1 = (int)((cur >> 8) & 255u) - o1,
               l2 = (int)((cur >> 16) & 255u) - o2;
+    int cbase;
+    if constexpr (TD == 3) cbase = (l0 * pe1 + l1) * pe2 + l2;
+    else if constexpr (TD == 2) cbase = l1 * pe2 + l2;
+    else cbase = l2;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
       if (!pv[k]) continue;
+      const int b = cbase + loff[k];
 #pragma unroll
       for (int i = 0; i < NI0; ++i) {
-        int cell;
-        if constexpr (TD == 3) cell = ((l0 + i) * pe1 + l1 + i1[k]) * pe2 + l2 + i2[k];
-        else if constexpr (TD == 2) cell = (l1 + i1[k]) * pe2 + l2 + i2[k];
-        else cell = l2 + i2[k];
-        const long long qv = __double2ll_rn((double)accr[k][i] * scale);
-        atomicAdd(&acc[cell], (unsigned long long)qv);
+        SAcc qv;
+        if constexpr (sizeof(T) == 4) qv = __float2int_rn(accr[k][i]);
+        else qv = __double2ll_rn(accr[k][i]);
+        atomicAdd(&acc[b + i * s01], (Acc)qv);
         accr[k][i] = (T)0;
       }
     }
@@ -191,10 +219,10 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     const T f0 = (ok && TD == 3) ? g_frac[p] : (T)0;
     const T f1 = (ok && TD >= 2) ? g_frac[LN + p] : (T)0;
     const T f2 = ok ? g_frac[2 * LN + p] : (T)0;
-    const T vv = ok ? v[g_idx[p]] : (T)0;
+    const T vv = ok ? v[g_idx[p]] * scale_t : (T)0;
     const int cnt = min(64, q1 - base_p);
     for (int q = 0; q < cnt; ++q) {
-      const unsigned bq = lane_bcast(mb, q);
+      const unsigned bq = __builtin_amdgcn_readfirstlane(lane_bcast(mb, q));
       if (bq != cur) {
         if (cur != kNone) flush();
         cur = bq;
@@ -218,12 +246,13 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
       if constexpr (TD == 3) {
         const T x0 = (T)2 * lane_bcast(f0, q) - (T)1;
         const T p0 = horner<T, K>(c0, x0);          // tap (lane % W) of the first dimension
+        T s0[W];
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-          const T s0 = lane_bcast(p0, i);
+        for (int i = 0; i < W; ++i) s0[i] = lane_bcast(p0, i);
 #pragma unroll
-          for (int k = 0; k < NP; ++k) accr[k][i] += w12[k] * s0;
-        }
+        for (int i = 0; i < W; ++i)
+#pragma unroll
+          for (int k = 0; k < NP; ++k) accr[k][i] += w12[k] * s0[i];
       } else {
 #pragma unroll
         for (int k = 0; k < NP; ++k) accr[k][0] += w12[k];
@@ -234,7 +263,7 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   __syncthreads();
   const double inv = 1.0 / scale;
   for (int c = threadIdx.x; c < cells; c += kSpreadThreads)
-    out[c] = (T)((double)(long long)acc[c] * inv);
+    out[c] = (T)((double)(SAcc)acc[c] * inv);
 }
 
 // Fold: every grid cell sums, in fixed order, the padded-tile slots that cover it.  Along each
@@ -249,11 +278,11 @@ k_fold(const WinDev* __restrict__ wins, const FoldJob* __restrict__ jobs,
   const WinDev& w = wins[job.win];
   if (check && imgs[w.img].st->done) return;
   if ((int)threadIdx.x >= job.ncell) return;
-  const T* __restrict__ padded = reinterpret_cast<const T*>(w.padded);
+  GlobalPtr<T> padded = (GlobalPtr<T>)w.padded;
   const long long slot_stride = w.slot_stride;
-  const int* __restrict__ tile_slot0 = w.tile_slot0;
-  const int* __restrict__ tile_nslot = w.tile_nslot;
-  T* __restrict__ grid = reinterpret_cast<T*>(w.grid);
+  ConstPtr<int> tile_slot0 = (ConstPtr<int>)w.tile_slot0;
+  ConstPtr<int> tile_nslot = (ConstPtr<int>)w.tile_nslot;
+  T __attribute__((address_space(1)))* grid = (T __attribute__((address_space(1)))*)w.grid;
   const long long c = job.cell0 + threadIdx.x;
   int ct[3][3], cl[3][3], cn[3];
   {
@@ -294,7 +323,7 @@ k_fold(const WinDev* __restrict__ wins, const FoldJob* __restrict__ jobs,
         const int ns = tile_nslot[gt];
         if (ns == 0) continue;
         const long long pidx = ((long long)cl[0][a] * pe1 + cl[1][bq]) * pe2 + cl[2][e];
-        const T* src = padded + (long long)tile_slot0[gt] * slot_stride + pidx;
+        const auto src = padded + (long long)tile_slot0[gt] * slot_stride + pidx;
         for (int k = 0; k < ns; ++k) sum += src[(long long)k * slot_stride];
       }
   grid[w.grid_off + c] = sum;
@@ -311,11 +340,11 @@ k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int 
   const Fold3Job job = jobs[job0 + blockIdx.x];
   const WinDev& w = wins[job.win];
   if (check && imgs[w.img].st->done) return;
-  const T* __restrict__ padded = reinterpret_cast<const T*>(w.padded);
+  GlobalPtr<T> padded = (GlobalPtr<T>)w.padded;
   const long long slot_stride = w.slot_stride;
-  const int* __restrict__ tile_slot0 = w.tile_slot0;
-  const int* __restrict__ tile_nslot = w.tile_nslot;
-  T* __restrict__ grid = reinterpret_cast<T*>(w.grid);
+  ConstPtr<int> tile_slot0 = (ConstPtr<int>)w.tile_slot0;
+  ConstPtr<int> tile_nslot = (ConstPtr<int>)w.tile_nslot;
+  T __attribute__((address_space(1)))* grid = (T __attribute__((address_space(1)))*)w.grid;
   const int x2 = threadIdx.x % TS, x1 = threadIdx.x / TS;
   const int tc2 = job.tile & (w.nts[2] - 1);
   const int tc1 = (job.tile >> w.lnts[2]) & (w.nts[1] - 1);
@@ -343,11 +372,11 @@ k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int 
         if (ns == 0) continue;
         const int p1 = x1 - s1, p2 = x2 - s2;        // padded indices of this column
         if (p1 < 0 || p1 >= pe || p2 < 0 || p2 >= pe) continue;
-        const T* src = padded + (long long)tile_slot0[gt] * slot_stride + p1 * pe2 + p2;
+        const auto src = padded + (long long)tile_slot0[gt] * slot_stride + p1 * pe2 + p2;
 #pragma unroll
         for (int x0 = 0; x0 < TS; ++x0) {
           if (x0 < lo0 || x0 >= hi0) continue;
-          const T* q = src + (long long)(x0 - s0) * pe12;
+          const auto q = src + (long long)(x0 - s0) * pe12;
           T sum = (T)0;
           for (int k = 0; k < ns; ++k) sum += q[(long long)k * slot_stride];
           acc[x0] += sum;
@@ -355,7 +384,7 @@ k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int 
       }
     }
   }
-  T* g = grid + w.grid_off;
+  auto g = grid + w.grid_off;
   const int o0 = tc0 * TS, o1 = tc1 * TS, o2 = tc2 * TS;
 #pragma unroll
   for (int x0 = 0; x0 < TS; ++x0)
@@ -443,7 +472,7 @@ k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int jo
   const ConvJob job = jobs[job0 + blockIdx.x];
   const WinDev& w = wins[job.win];
   if (check && imgs[w.img].st->done) return;
-  T* __restrict__ grid = reinterpret_cast<T*>(w.grid);
+  T __attribute__((address_space(1)))* grid = (T __attribute__((address_space(1)))*)w.grid;
   using S = FftShape<N>;
   constexpr int A = S::A, B = S::B, CL = S::CL, RL = S::RL, SP = S::SP;
   extern __shared__ unsigned char smem_raw[];
@@ -460,7 +489,7 @@ k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int jo
   if (axis == 2) { es = 1; ls = N; }
   else if (axis == 1) { es = w.n[2]; ls = 1; }
   else { es = (long long)w.n[1] * w.n[2]; ls = 1; }
-  T* g = grid + w.grid_off + job.off;
+  auto g = grid + w.grid_off + job.off;
   const int nl = job.nl;
   for (int idx = threadIdx.x; idx < RL * N; idx += 256) {
     int ln, c;
@@ -471,7 +500,7 @@ k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int jo
   __syncthreads();
   const int ql = threadIdx.x / B, j1 = threadIdx.x % B;
   const bool act = ql < CL;
-  const T* coef = reinterpret_cast<const T*>(w.coef) + (long long)axis * w.n_max;
+  GlobalPtr<T> coef = (GlobalPtr<T>)w.coef + (long long)axis * w.n_max;
   Cx<T> v[A];
   if (act) {
 #pragma unroll
@@ -536,58 +565,30 @@ k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int jo
 }
 
 // ---------------------------------------------------------------------------- gathering
-// One thread per node.  Chunks with many nodes first stage the padded tile of the convolved
-// grid in LDS; small chunks read the grid directly.
-constexpr int kStageMin = 192;
+// One thread per node.  Chunks with enough nodes first stage the padded tile of the convolved
+// grid in LDS; small chunks read the grid directly.  The two cases are separate instantiations
+// of the node loop, so the staged one reads through an LDS pointer (ds_read) rather than a
+// generic one (flat loads).
 
-template <typename T, int W, int TD>
-__global__ void __launch_bounds__(kGatherThreads)
-k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int job0,
-         const ImgDev* __restrict__ imgs, int check) {
-  const TileJob job = jobs[job0 + blockIdx.x];
-  const WinDev& w = wins[job.win];
-  if (check && imgs[w.img].st->done) return;
-  extern __shared__ unsigned char smem_raw[];
-  T* tile = reinterpret_cast<T*>(smem_raw);
-  const int* __restrict__ g_idx = w.g_idx;
-  const unsigned* __restrict__ g_base = w.g_base;
-  const T* __restrict__ g_frac = reinterpret_cast<const T*>(w.g_frac);
-  const long long LN = w.LN;
-  T* __restrict__ ylocal = reinterpret_cast<T*>(w.ylocal);
-  const T* h = reinterpret_cast<const T*>(w.grid) + w.grid_off;
-  const int n0 = w.n[0], n1 = w.n[1], n2 = w.n[2];
-  const int pe0 = w.pe[0], pe1 = w.pe[1], pe2 = w.pe[2];
-  const int o0 = tile_origin(w, job.tile, 0), o1 = tile_origin(w, job.tile, 1),
-            o2 = tile_origin(w, job.tile, 2);
+template <typename T, int W, int TD, bool STAGED, typename PP>
+__device__ __forceinline__ void gather_nodes(const TileJob& job, const WinDev& w,
+                                             const T* __restrict__ tile, const T* __restrict__ h,
+                                             PP psi, int o0, int o1, int o2) {
   constexpr int m = W / 2;
-  // first grid cell covered by the padded tile, per dimension
-  const int s0 = (TD == 3) ? o0 - m + 1 : o0;
-  const int s1 = (TD >= 2) ? o1 - m + 1 : o1;
-  const int s2 = o2 - m + 1;
-  const bool staged = (job.pend - job.pbeg) >= kStageMin;
-  if (staged) {
-    const int cells = pe0 * pe1 * pe2;
-    for (int c = threadIdx.x; c < cells; c += kGatherThreads) {
-      const int a2 = c % pe2, a1 = (c / pe2) % pe1, a0 = c / (pe2 * pe1);
-      const int g0 = wrap(s0 + a0, n0), g1 = wrap(s1 + a1, n1), g2 = wrap(s2 + a2, n2);
-      tile[c] = h[((long long)g0 * n1 + g1) * n2 + g2];
-    }
-    __syncthreads();
-  }
-  // window polynomials: from global (scalar loads) when small, else staged in LDS
-  constexpr int KP = PsiDeg<T>::value + 1;
-  constexpr bool PSI_LDS = (W * KP * (int)sizeof(T) / 4) > 96;
-  __shared__ T s_psi[PSI_LDS ? W * KP : 1];
-  const T* psi = reinterpret_cast<const T*>(w.psi);
-  if constexpr (PSI_LDS) {
-    for (int c = threadIdx.x; c < W * KP; c += kGatherThreads) s_psi[c] = psi[c];
-    __syncthreads();
-    psi = s_psi;
-  }
-  constexpr int K = KP;
+  constexpr int K = PsiDeg<T>::value + 1;
   // large rows (FP64, m >= 6): evaluate the middle dimension's weights inside the loop instead of
   // keeping a second register row, to stay within the register file
   constexpr bool BIG = W * (int)sizeof(T) > 64;
+  GlobalPtr<int> g_idx = (GlobalPtr<int>)w.g_idx;
+  GlobalPtr<unsigned> g_base = (GlobalPtr<unsigned>)w.g_base;
+  GlobalPtr<T> g_frac = (GlobalPtr<T>)w.g_frac;
+  const long long LN = w.LN;
+  T* __restrict__ ylocal = reinterpret_cast<T*>(w.ylocal);
+  const int n0 = w.n[0], n1 = w.n[1], n2 = w.n[2];
+  const int pe1 = w.pe[1], pe2 = w.pe[2];
+  // explicit address spaces: LDS reads for the staged tile, global loads otherwise
+  LdsPtr<T> tile_l = (LdsPtr<T>)tile;
+  GlobalPtr<T> h_g = (GlobalPtr<T>)h;
   for (int p = job.pbeg + threadIdx.x; p < job.pend; p += kGatherThreads) {
     const unsigned bb = g_base[p];
     const int b2 = (int)((bb >> 16) & 255u), b1 = (int)((bb >> 8) & 255u), b0 = (int)(bb & 255u);
@@ -599,15 +600,18 @@ k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     const T x0 = (TD == 3) ? (T)2 * g_frac[p] - (T)1 : (T)0;
     int c2[W];
 #pragma unroll
-    for (int i2 = 0; i2 < W; ++i2) c2[i2] = staged ? b2 - o2 + i2 : wrap(b2 - m + 1 + i2, n2);
+    for (int i2 = 0; i2 < W; ++i2) c2[i2] = STAGED ? b2 - o2 + i2 : wrap(b2 - m + 1 + i2, n2);
     // row start of (i0, i1) in the staged tile or in the grid
-    auto row_of = [&](int i0, int i1) -> const T* {
-      if (staged) return tile + ((b0 - o0 + i0) * pe1 + (b1 - o1 + i1)) * pe2;
-      const int g0 = (TD == 3) ? wrap(b0 - m + 1 + i0, n0) : 0;
-      const int g1 = (TD >= 2) ? wrap(b1 - m + 1 + i1, n1) : 0;
-      return h + ((long long)g0 * n1 + g1) * n2;
+    auto row_of = [&](int i0, int i1) {
+      if constexpr (STAGED) {
+        return tile_l + ((b0 - o0 + i0) * pe1 + (b1 - o1 + i1)) * pe2;
+      } else {
+        const int g0 = (TD == 3) ? wrap(b0 - m + 1 + i0, n0) : 0;
+        const int g1 = (TD >= 2) ? wrap(b1 - m + 1 + i1, n1) : 0;
+        return h_g + ((long long)g0 * n1 + g1) * n2;
+      }
     };
-    auto line = [&](const T* row) {
+    auto line = [&](auto row) {
       T sacc = (T)0;
 #pragma unroll
       for (int i2 = 0; i2 < W; ++i2) sacc += row[c2[i2]] * w2[i2];
@@ -632,6 +636,54 @@ k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
       acc = plane(0);
     }
     ylocal[g_idx[p]] = acc;
+  }
+}
+
+template <typename T, int W, int TD>
+__global__ void __launch_bounds__(kGatherThreads)
+k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int job0,
+         const ImgDev* __restrict__ imgs, int check, int stage_min) {
+  const TileJob job = jobs[job0 + blockIdx.x];
+  const WinDev& w = wins[job.win];
+  if (check && imgs[w.img].st->done) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* tile = reinterpret_cast<T*>(smem_raw);
+  const T* h = reinterpret_cast<const T*>(w.grid) + w.grid_off;
+  const int n0 = w.n[0], n1 = w.n[1], n2 = w.n[2];
+  const int pe0 = w.pe[0], pe1 = w.pe[1], pe2 = w.pe[2];
+  const int o0 = tile_origin(w, job.tile, 0), o1 = tile_origin(w, job.tile, 1),
+            o2 = tile_origin(w, job.tile, 2);
+  constexpr int m = W / 2;
+  // window polynomials: from global (scalar loads) when small, else staged in LDS
+  constexpr int KP = PsiDeg<T>::value + 1;
+  constexpr bool PSI_LDS = (W * KP * (int)sizeof(T) / 4) > 96;
+  __shared__ T s_psi[PSI_LDS ? W * KP : 1];
+  const T* psi_g = reinterpret_cast<const T*>(w.psi);
+  if constexpr (PSI_LDS) {
+    for (int c = threadIdx.x; c < W * KP; c += kGatherThreads) s_psi[c] = psi_g[c];
+  }
+  const bool staged = (job.pend - job.pbeg) >= stage_min;
+  if (staged) {
+    // first grid cell covered by the padded tile, per dimension
+    const int s0 = (TD == 3) ? o0 - m + 1 : o0;
+    const int s1 = (TD >= 2) ? o1 - m + 1 : o1;
+    const int s2 = o2 - m + 1;
+    const int cells = pe0 * pe1 * pe2;
+    for (int c = threadIdx.x; c < cells; c += kGatherThreads) {
+      const int a2 = c % pe2, a1 = (c / pe2) % pe1, a0 = c / (pe2 * pe1);
+      const int g0 = wrap(s0 + a0, n0), g1 = wrap(s1 + a1, n1), g2 = wrap(s2 + a2, n2);
+      tile[c] = h[((long long)g0 * n1 + g1) * n2 + g2];
+    }
+    __syncthreads();
+    if constexpr (PSI_LDS) gather_nodes<T, W, TD, true>(job, w, tile, h, (LdsPtr<T>)s_psi, o0, o1, o2);
+    else gather_nodes<T, W, TD, true>(job, w, tile, h, (ConstPtr<T>)psi_g, o0, o1, o2);
+  } else {
+    if constexpr (PSI_LDS) {
+      __syncthreads();
+      gather_nodes<T, W, TD, false>(job, w, tile, h, (LdsPtr<T>)s_psi, o0, o1, o2);
+    } else {
+      gather_nodes<T, W, TD, false>(job, w, tile, h, (ConstPtr<T>)psi_g, o0, o1, o2);
+    }
   }
 }
 
@@ -754,9 +806,20 @@ void allow_lds(K k, size_t lds) {
     NLD_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
 }
 
+// Chunks with at least this many nodes stage the padded tile of the convolved grid in LDS for
+// the gathering (a tile is read once instead of 8^t scattered reads per node).
+int gather_stage_min() {
+  static const int v = [] {
+    const char* e = std::getenv("NLD_GATHER_STAGE_MIN");
+    return e ? std::max(1, std::atoi(e)) : 1;
+  }();
+  return v;
+}
+
 template <typename T, int W>
 void launch_tiles(const LaunchSet& ls, VecArg in, int check, hipStream_t s, bool gather) {
-  const size_t lds = (size_t)ls.max_padded * (gather ? sizeof(T) : sizeof(double));
+  // spreading accumulates in 32-bit (FP32) or 64-bit (FP64) fixed point: sizeof(T) per cell
+  const size_t lds = (size_t)ls.max_padded * sizeof(T);
   for (int g = 0; g < 3; ++g) {
     const int j0 = ls.tjob_begin[g], nj = ls.tjob_begin[g + 1] - j0;
     if (nj == 0) continue;
@@ -769,7 +832,7 @@ void launch_tiles(const LaunchSet& ls, VecArg in, int check, hipStream_t s, bool
       auto k = (g == 0) ? k_gather<T, W, 1> : (g == 1) ? k_gather<T, W, 2> : k_gather<T, W, 3>;
       allow_lds(k, lds);
       hipLaunchKernelGGL(k, dim3(nj), dim3(kGatherThreads), lds, s, ls.d_wins, ls.d_tjobs, j0,
-                         ls.d_imgs, check);
+                         ls.d_imgs, check, gather_stage_min());
     }
     NLD_HIP(hipGetLastError());
   }

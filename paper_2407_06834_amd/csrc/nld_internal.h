@@ -84,8 +84,9 @@ struct VecArg {
 
 // Degree of the per-tap polynomial that replaces the window evaluation: the scaled
 // Kaiser-Bessel window is an entire function of the distance, so a Chebyshev interpolant on each
-// unit interval converges fast (max error ~6e-9 at degree 8 and ~3e-15 at degree 14 for m = 4..8).
-template <typename T> struct PsiDeg { static constexpr int value = sizeof(T) == 4 ? 8 : 14; };
+// unit interval converges fast (max error ~4e-8 at degree 7, below FP32 rounding, and ~3e-15 at
+// degree 14 for m = 3..8).
+template <typename T> struct PsiDeg { static constexpr int value = sizeof(T) == 4 ? 7 : 14; };
 
 struct TileJob {       // a chunk of the nodes of one tile (spreading and gathering)
   int win, tile, pbeg, pend, slot;   // pbeg/pend: positions in the sorted node list
