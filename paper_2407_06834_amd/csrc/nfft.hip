@@ -564,6 +564,128 @@ k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int jo
   }
 }
 
+// ---------------------------------------------------------------------------- plane kernel
+// The convolutions along the last two dimensions of a 3-D window (FP32, n = N <= 128), one
+// workgroup per grid plane i0: the plane is read into LDS once, its lines are convolved along
+// the last and then the middle dimension in LDS (same four-step arithmetic as k_conv, so the
+// result is bitwise that of two convolution passes), and the plane is written once.  Saves one
+// read/write pass over the grid.  (Folding the padded-tile slots straight into the plane was
+// measured slower than the separate per-tile fold, which shares its neighbour lookups across a
+// tile's planes.)
+template <int N> struct PlaneShape {
+  static constexpr int A = (N >= 128) ? 16 : 8;
+  static constexpr int B = N / A;
+  static constexpr int CL = N / 2;                // complex lines: every line of the plane
+  static constexpr int THREADS = 512;
+  static constexpr int PS = N + 1;                // plane row stride (floats)
+  static constexpr int XS = N + 1;                // exchange line stride (complex), aliasing the plane
+  static constexpr size_t lds() {
+    const size_t plane = (size_t)N * PS * sizeof(float), exch = (size_t)CL * XS * 2 * sizeof(float);
+    return (plane > exch ? plane : exch) + (size_t)N * 2 * sizeof(float);
+  }
+  static_assert(CL * B <= THREADS, "plane lines exceed the workgroup");
+};
+
+template <int N>
+__global__ void __launch_bounds__(512)
+k_plane(const WinDev* __restrict__ wins, const PlaneJob* __restrict__ jobs, int job0,
+        const ImgDev* __restrict__ imgs, int check) {
+  using T = float;
+  using S = PlaneShape<N>;
+  constexpr int A = S::A, B = S::B, CL = S::CL, PS = S::PS, XS = S::XS;
+  const PlaneJob job = jobs[job0 + blockIdx.x];
+  const WinDev& w = wins[job.win];
+  if (check && imgs[w.img].st->done) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* plane = reinterpret_cast<T*>(smem_raw);
+  Cx<T>* ex = reinterpret_cast<Cx<T>*>(smem_raw);   // the same bytes, used while lines are in registers
+  constexpr size_t kMain = (size_t)N * PS * sizeof(T) > (size_t)CL * XS * 2 * sizeof(T)
+                               ? (size_t)N * PS * sizeof(T) : (size_t)CL * XS * 2 * sizeof(T);
+  Cx<T>* tw = reinterpret_cast<Cx<T>*>(smem_raw + kMain);
+  const int tid = threadIdx.x;
+  for (int q = tid; q < N; q += S::THREADS) {
+    T sn, cs;
+    sincospif(-2.0f * (float)q / (float)N, &sn, &cs);
+    tw[q] = {cs, sn};
+  }
+  // ---- the folded plane into LDS
+  T __attribute__((address_space(1)))* g =
+      (T __attribute__((address_space(1)))*)w.grid + w.grid_off + (long long)job.i0 * N * N;
+  for (int idx = tid; idx < N * N; idx += S::THREADS) {
+    const int i1 = idx / N, i2 = idx - i1 * N;
+    plane[i1 * PS + i2] = g[idx];
+  }
+  __syncthreads();
+  // ---- convolution of every line along the last (rows) and then the middle (columns) dimension
+  const int ql = tid / B, j1 = tid % B;
+  const bool act = ql < CL;
+  GlobalPtr<T> coef_all = (GlobalPtr<T>)w.coef;
+  for (int axis = 2; axis >= 1; --axis) {
+    const int ls = (axis == 2) ? PS : 1, es = (axis == 2) ? 1 : PS;
+    GlobalPtr<T> coef = coef_all + (long long)axis * w.n_max;
+    Cx<T> v[A];
+    if (act) {
+#pragma unroll
+      for (int j2 = 0; j2 < A; ++j2) {
+        const int c = j1 + B * j2;
+        v[j2] = {plane[(2 * ql) * ls + c * es], plane[(2 * ql + 1) * ls + c * es]};
+      }
+      dft_reg<T, A, false>(v);
+#pragma unroll
+      for (int k2 = 0; k2 < A; ++k2) v[k2] = cmul(v[k2], tw[(j1 * k2) & (N - 1)]);
+    }
+    __syncthreads();   // every line is in registers: the plane's bytes become the exchange buffer
+    if (act) {
+#pragma unroll
+      for (int k2 = 0; k2 < A; ++k2) ex[ql * XS + k2 * B + j1] = v[k2];
+    }
+    __syncthreads();
+    constexpr int R = A / B > 0 ? A / B : 1;
+    if (act) {
+      Cx<T> u[R][B];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int k2 = j1 * R + r;
+#pragma unroll
+        for (int k1 = 0; k1 < B; ++k1) u[r][k1] = ex[ql * XS + k2 * B + k1];
+        dft_reg<T, B, false>(u[r]);
+#pragma unroll
+        for (int k1 = 0; k1 < B; ++k1) {
+          const T cm = coef[k2 + A * k1];
+          u[r][k1].x *= cm;
+          u[r][k1].y *= cm;
+        }
+        dft_reg<T, B, true>(u[r]);
+#pragma unroll
+        for (int j = 0; j < B; ++j) u[r][j] = cmulc(u[r][j], tw[(j * k2) & (N - 1)]);
+#pragma unroll
+        for (int j = 0; j < B; ++j) ex[ql * XS + k2 * B + j] = u[r][j];
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int k2 = 0; k2 < A; ++k2) v[k2] = ex[ql * XS + k2 * B + j1];
+      dft_reg<T, A, true>(v);
+    }
+    __syncthreads();   // the exchange buffer is read: its bytes hold the plane again
+    if (act) {
+#pragma unroll
+      for (int j2 = 0; j2 < A; ++j2) {
+        const int c = j1 + B * j2;
+        plane[(2 * ql) * ls + c * es] = v[j2].x;
+        plane[(2 * ql + 1) * ls + c * es] = v[j2].y;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- write the plane
+  for (int idx = tid; idx < N * N; idx += S::THREADS) {
+    const int i1 = idx / N, i2 = idx - i1 * N;
+    g[idx] = plane[i1 * PS + i2];
+  }
+}
+
 // ---------------------------------------------------------------------------- gathering
 // One thread per node.  Chunks with enough nodes first stage the padded tile of the convolved
 // grid in LDS; small chunks read the grid directly.  The two cases are separate instantiations
@@ -863,6 +985,22 @@ void launch_conv(const LaunchSet& ls, int ax, int j0, int nj, int check, hipStre
   NLD_HIP(hipGetLastError());
 }
 
+template <int N>
+void launch_plane(const LaunchSet& ls, int j0, int nj, int check, hipStream_t s) {
+  const size_t lds = PlaneShape<N>::lds();
+  allow_lds(k_plane<N>, lds);
+  hipLaunchKernelGGL(k_plane<N>, dim3(nj), dim3(PlaneShape<N>::THREADS), lds, s, ls.d_wins,
+                     ls.d_pjobs, j0, ls.d_imgs, check);
+  NLD_HIP(hipGetLastError());
+}
+
+// fused convolution of the last two dimensions, per grid plane (FP32 3-D windows)
+void planes_all(const LaunchSet& ls, int check, hipStream_t s) {
+  const int n64 = ls.pjob_begin[1] - ls.pjob_begin[0], n128 = ls.pjob_begin[2] - ls.pjob_begin[1];
+  if (n64 > 0) launch_plane<64>(ls, ls.pjob_begin[0], n64, check, s);
+  if (n128 > 0) launch_plane<128>(ls, ls.pjob_begin[1], n128, check, s);
+}
+
 template <typename T>
 void conv_all(const LaunchSet& ls, int check, hipStream_t s) {
   for (int ax = 2; ax >= 0; --ax) {
@@ -926,15 +1064,15 @@ void matvec_parts_t(Plan& P, const void* v, void* yk, void* yks, hipStream_t s) 
   const long long LN = (long long)P.N * P.L;
   const size_t gbytes = (size_t)P.grid_total * sizeof(T);
   const VecArg in{v, 0};
-  spread_fold<T>(P.ls, in, 0, s);
+  spread_fold<T>(P.ls_unfused, in, 0, s);
   NLD_HIP(hipMemcpyAsync(P.grid_save, P.grid, gbytes, hipMemcpyDeviceToDevice, s));
-  conv_all<T>(P.ls, 0, s);
-  tiles_dispatch<T>(P.ls, in, 0, s, true);
+  conv_all<T>(P.ls_unfused, 0, s);
+  tiles_dispatch<T>(P.ls_unfused, in, 0, s, true);
   NLD_HIP(hipMemcpyAsync(yk, P.ylocal, LN * sizeof(T), hipMemcpyDeviceToDevice, s));
   bool first = true;
   for (int d = 0; d < 3; ++d) {
     if (!P.dv_used[d]) continue;
-    LaunchSet lsd = P.ls;
+    LaunchSet lsd = P.ls_unfused;
     lsd.d_wins = P.d_wins_dv[d];
     NLD_HIP(hipMemcpyAsync(P.grid, P.grid_save, gbytes, hipMemcpyDeviceToDevice, s));
     conv_all<T>(lsd, 0, s);
@@ -1021,6 +1159,7 @@ void matvec_set_t(const LaunchSet& ls, VecArg in, VecArg out, double* Dout, Epil
   // only the iteration's product stops early once a solve has finished
   const int check = (epi == EPI_CG_Q) ? 1 : 0;
   spread_fold<T>(ls, in, check, s);
+  planes_all(ls, check, s);
   conv_all<T>(ls, check, s);
   tiles_dispatch<T>(ls, in, check, s, true);
   ReduceArgs a;

@@ -98,6 +98,9 @@ struct FoldJob {       // 256 consecutive cells of one window's grid
 struct Fold3Job {      // one tile of a 3-D window
   int win, tile;
 };
+struct PlaneJob {     // one grid plane of a 3-D window (two fused convolution passes)
+  int win, i0;
+};
 struct ConvJob {
   int win;
   int nl;              // lines in this job (<= lines per workgroup)
@@ -137,6 +140,8 @@ struct LaunchSet {
   int n_fjobs = 0;
   const ConvJob* d_conv[3] = {nullptr, nullptr, nullptr};
   int conv_begin[3][5] = {{0}};                 // per axis, grid size n = 32 << g
+  const PlaneJob* d_pjobs = nullptr;
+  int pjob_begin[3] = {0, 0, 0};                // n = 64: [0], [1]); n = 128: [1], [2])
   ImgDev* d_imgs = nullptr;
   int n_imgs = 0;
   long long max_N = 0;
@@ -217,8 +222,11 @@ struct Plan {
   double* red = nullptr;           // reduction partials [kRedBlocks][8]
   CgState* st = nullptr;           // device CG state
   CgState* st_host = nullptr;      // pinned mirror
-  // launch description of this plan alone, its image table and a pinned host mirror of it
+  // launch description of this plan alone, its image table and a pinned host mirror of it; the
+  // fused schedule (plane kernels) and the unfused one (three convolution passes), which the
+  // per-window products of the gradient use
   LaunchSet ls;
+  LaunchSet ls_unfused;
   ImgDev* d_img = nullptr;
   ImgDev* img_host = nullptr;
   // host copies of the schedules (a batch concatenates them)
@@ -226,6 +234,13 @@ struct Plan {
   std::vector<Fold3Job> h_f3jobs;
   std::vector<FoldJob> h_fjobs;
   std::vector<ConvJob> h_conv[3];
+  std::vector<PlaneJob> h_pjobs;
+  int pjob_begin[3] = {0, 0, 0};
+  PlaneJob* d_pjobs = nullptr;
+  Fold3Job* d_f3jobs_u = nullptr;               // unfused schedule (device only)
+  int n_f3jobs_u = 0;
+  ConvJob* d_conv_u[3] = {nullptr, nullptr, nullptr};
+  int conv_begin_u[3][5] = {{0}};
   int tile3 = 0;                   // requested tile extent of 3-D windows (0: default)
 };
 

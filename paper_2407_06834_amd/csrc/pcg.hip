@@ -456,6 +456,7 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
     std::vector<Fold3Job> f3[2];
     std::vector<FoldJob> fj;
     std::vector<ConvJob> cj[3][4];
+    std::vector<PlaneJob> pj[2];
     std::vector<ImgDev> imgs(count);
     LaunchSet ls;
     ls.prec = plans[0]->prec;
@@ -489,6 +490,12 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
         j.win += wo;
         fj.push_back(j);
       }
+      for (int gi = 0; gi < 2; ++gi)
+        for (int j = P.pjob_begin[gi]; j < P.pjob_begin[gi + 1]; ++j) {
+          PlaneJob q = P.h_pjobs[j];
+          q.win += wo;
+          pj[gi].push_back(q);
+        }
       for (int ax = 0; ax < 3; ++ax)
         for (int gi = 0; gi < 4; ++gi)
           for (int j = P.conv_begin[ax][gi]; j < P.conv_begin[ax][gi + 1]; ++j) {
@@ -536,6 +543,14 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
       }
       ls.conv_begin[ax][4] = (int)all.size();
       ls.d_conv[ax] = dev_copy(all, cs, owned);
+    }
+    {
+      std::vector<PlaneJob> all(pj[0]);
+      all.insert(all.end(), pj[1].begin(), pj[1].end());
+      ls.pjob_begin[0] = 0;
+      ls.pjob_begin[1] = (int)pj[0].size();
+      ls.pjob_begin[2] = (int)all.size();
+      ls.d_pjobs = dev_copy(all, cs, owned);
     }
     ls.d_imgs = dev_copy(imgs, cs, owned);
 

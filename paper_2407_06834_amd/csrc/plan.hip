@@ -790,48 +790,86 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     }
   }
   P.h_fjobs = fj;
-  P.h_f3jobs = f3;
   P.n_fjobs = (int)fj.size();
   P.d_fjobs = dalloc<FoldJob>(std::max<size_t>(1, fj.size()), s);
   NLD_HIP(hipMemcpyAsync(P.d_fjobs, fj.data(), fj.size() * sizeof(FoldJob), hipMemcpyHostToDevice, s));
-  P.n_f3jobs = (int)f3.size();
-  P.d_f3jobs = dalloc<Fold3Job>(std::max<size_t>(1, f3.size()), s);
-  NLD_HIP(hipMemcpyAsync(P.d_f3jobs, f3.data(), f3.size() * sizeof(Fold3Job), hipMemcpyHostToDevice, s));
+  // windows whose convolutions along the last two dimensions run fused per grid plane: FP32,
+  // three kept dimensions of n = 64 or 128 points (plane, exchange buffer and twiddles in LDS)
+  std::vector<char> fused(L, 0);
+  const bool no_plane = std::getenv("NLD_NO_PLANE") != nullptr;
+  for (int l = 0; l < L; ++l) {
+    const WinDev& w = P.wins[l];
+    const int n = w.n[0];
+    const long long need = std::max((long long)n * (n + 1) * 4, (long long)(n / 2) * (n + 1) * 8) +
+                           (long long)n * 8;
+    fused[l] = !no_plane && P.prec == NLD_FP32 && w.t == 3 && n == w.n[1] && n == w.n[2] &&
+               (n == 64 || n == 128) && need <= P.lds_limit;
+  }
+  std::vector<PlaneJob> pj;
+  for (int gi = 0; gi < 2; ++gi) {
+    P.pjob_begin[gi] = (int)pj.size();
+    const int ng = 64 << gi;
+    for (int l = 0; l < L; ++l)
+      if (fused[l] && P.wins[l].n[0] == ng)
+        for (int i0 = 0; i0 < ng; ++i0) pj.push_back(PlaneJob{l, i0});
+  }
+  P.pjob_begin[2] = (int)pj.size();
+  P.h_pjobs = pj;
+  P.d_pjobs = dalloc<PlaneJob>(std::max<size_t>(1, pj.size()), s);
+  NLD_HIP(hipMemcpyAsync(P.d_pjobs, pj.data(), pj.size() * sizeof(PlaneJob), hipMemcpyHostToDevice, s));
+  std::vector<Fold3Job> f3f(f3);                // the fold still runs for every window
+  P.h_f3jobs = f3f;
+  P.n_f3jobs = (int)f3f.size();
+  P.d_f3jobs = dalloc<Fold3Job>(std::max<size_t>(1, f3f.size()), s);
+  NLD_HIP(hipMemcpyAsync(P.d_f3jobs, f3f.data(), f3f.size() * sizeof(Fold3Job), hipMemcpyHostToDevice, s));
+  P.n_f3jobs_u = (int)f3.size();
+  P.d_f3jobs_u = dalloc<Fold3Job>(std::max<size_t>(1, f3.size()), s);
+  NLD_HIP(hipMemcpyAsync(P.d_f3jobs_u, f3.data(), f3.size() * sizeof(Fold3Job), hipMemcpyHostToDevice, s));
 
   // convolution jobs: for each axis, lines of every window that has that axis, grouped by the
   // grid size n; each job holds the real lines one workgroup transforms (64 for n = 64 and 128,
-  // 32 for n = 32 and 256), adjacent in memory along the contiguous dimension
-  std::vector<ConvJob> cjobs_all[3];
+  // 32 for n = 32 and 256), adjacent in memory along the contiguous dimension.  The fused
+  // schedule drops the last two axes of the fused windows.
+  std::vector<ConvJob> cjobs_all[3], cjobs_f[3];
   for (int ax = 0; ax < 3; ++ax) {
-    std::vector<ConvJob>& cjobs = cjobs_all[ax];
     for (int gi = 0; gi < 4; ++gi) {
-      P.conv_begin[ax][gi] = (int)cjobs.size();
+      P.conv_begin_u[ax][gi] = (int)cjobs_all[ax].size();
+      P.conv_begin[ax][gi] = (int)cjobs_f[ax].size();
       const int ng = 32 << gi;
       const int lines_per = (ng == 64 || ng == 128) ? 64 : 32;
       for (int l = 0; l < L; ++l) {
         const WinDev& w = P.wins[l];
         if (w.n[ax] == 1 || w.n[ax] != ng) continue;
         const int n0 = w.n[0], n1 = w.n[1], n2 = w.n[2];
+        std::vector<ConvJob> jl;
         if (ax == 2) {
           const long long lines = (long long)n0 * n1;
           for (long long q = 0; q < lines; q += lines_per)
-            cjobs.push_back(ConvJob{l, (int)std::min<long long>(lines_per, lines - q), q * n2});
+            jl.push_back(ConvJob{l, (int)std::min<long long>(lines_per, lines - q), q * n2});
         } else if (ax == 1) {
           for (int i0 = 0; i0 < n0; ++i0)
             for (int i2 = 0; i2 < n2; i2 += lines_per)
-              cjobs.push_back(ConvJob{l, std::min(lines_per, n2 - i2), (long long)i0 * n1 * n2 + i2});
+              jl.push_back(ConvJob{l, std::min(lines_per, n2 - i2), (long long)i0 * n1 * n2 + i2});
         } else {
           for (int i1 = 0; i1 < n1; ++i1)
             for (int i2 = 0; i2 < n2; i2 += lines_per)
-              cjobs.push_back(ConvJob{l, std::min(lines_per, n2 - i2), (long long)i1 * n2 + i2});
+              jl.push_back(ConvJob{l, std::min(lines_per, n2 - i2), (long long)i1 * n2 + i2});
         }
+        cjobs_all[ax].insert(cjobs_all[ax].end(), jl.begin(), jl.end());
+        if (!(fused[l] && ax != 0)) cjobs_f[ax].insert(cjobs_f[ax].end(), jl.begin(), jl.end());
       }
     }
-    P.conv_begin[ax][4] = (int)cjobs.size();
-    P.h_conv[ax] = cjobs;
-    if (!cjobs.empty()) {
-      P.d_conv[ax] = dalloc<ConvJob>(cjobs.size(), s);
-      NLD_HIP(hipMemcpyAsync(P.d_conv[ax], cjobs.data(), cjobs.size() * sizeof(ConvJob),
+    P.conv_begin_u[ax][4] = (int)cjobs_all[ax].size();
+    P.conv_begin[ax][4] = (int)cjobs_f[ax].size();
+    P.h_conv[ax] = cjobs_f[ax];
+    if (!cjobs_f[ax].empty()) {
+      P.d_conv[ax] = dalloc<ConvJob>(cjobs_f[ax].size(), s);
+      NLD_HIP(hipMemcpyAsync(P.d_conv[ax], cjobs_f[ax].data(), cjobs_f[ax].size() * sizeof(ConvJob),
+                             hipMemcpyHostToDevice, s));
+    }
+    if (!cjobs_all[ax].empty()) {
+      P.d_conv_u[ax] = dalloc<ConvJob>(cjobs_all[ax].size(), s);
+      NLD_HIP(hipMemcpyAsync(P.d_conv_u[ax], cjobs_all[ax].data(), cjobs_all[ax].size() * sizeof(ConvJob),
                              hipMemcpyHostToDevice, s));
     }
   }
@@ -915,11 +953,24 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     ls.d_conv[ax] = P.d_conv[ax];
     for (int g = 0; g < 5; ++g) ls.conv_begin[ax][g] = P.conv_begin[ax][g];
   }
+  ls.d_pjobs = P.d_pjobs;
+  for (int g = 0; g < 3; ++g) ls.pjob_begin[g] = P.pjob_begin[g];
   ls.d_imgs = P.d_img;
   ls.n_imgs = 1;
   ls.max_N = N;
   ls.max_nred = nred;
   ls.has_flat = P.has_flat;
+  LaunchSet& lu = P.ls_unfused;
+  lu = ls;
+  lu.d_f3jobs = P.d_f3jobs_u;
+  lu.f3_begin[1] = (P.f3_ts == 16) ? 0 : P.n_f3jobs_u;
+  lu.f3_begin[2] = P.n_f3jobs_u;
+  for (int ax = 0; ax < 3; ++ax) {
+    lu.d_conv[ax] = P.d_conv_u[ax];
+    for (int g = 0; g < 5; ++g) lu.conv_begin[ax][g] = P.conv_begin_u[ax][g];
+  }
+  lu.d_pjobs = nullptr;
+  for (int g = 0; g < 3; ++g) lu.pjob_begin[g] = 0;
 
   dfree(d_cp, s);
   dfree(base, s);
@@ -1003,7 +1054,8 @@ void release_plan(Plan& P) {
                   P.tile_nslot, P.ylocal, P.D, P.sumv, P.ones, P.psi, P.d_tjobs, P.d_fjobs, P.d_f3jobs, P.d_conv[0], P.d_conv[1],
                   P.d_conv[2], P.z, P.r, P.p, P.q, P.red, P.st, P.coef_dv, P.d_wins_dv[0],
                   P.d_wins_dv[1], P.d_wins_dv[2], P.grid_save, P.yk, P.yks, P.dl, P.dls,
-                  P.adj_part, P.d_img};
+                  P.adj_part, P.d_img, P.d_pjobs, P.d_f3jobs_u, P.d_conv_u[0], P.d_conv_u[1],
+                  P.d_conv_u[2]};
   for (void* b : bufs) dfree(b, s);
   (void)hipStreamSynchronize(s);
   if (P.img_host) (void)hipHostFree(P.img_host);

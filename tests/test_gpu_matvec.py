@@ -7,7 +7,7 @@ from oracle import kernel as K
 from oracle import nfft as ON
 from oracle.features import features_from_image as o_features
 from oracle.features import window_table as o_windows
-from paper_2407_06834_amd.synth import make_image
+from paper_2407_06834_amd.synth import make_image, random_vector
 
 pytestmark = pytest.mark.gpu
 
@@ -175,3 +175,28 @@ def test_single_pixel_image():
     assert plan.laplacian_matvec(v).item() == 0.0
     u, info = plan.pcg_solve(1.0, v, tol=1e-8)
     assert info["iters"] == 0 and u.item() == 1.7
+
+
+@pytest.mark.parametrize("bandwidth", [32, 64])
+def test_fused_plane_schedule_is_bitwise_equal_to_unfused(bandwidth):
+    """FP32 3-D windows fold and convolve two dimensions per grid plane in one kernel; the
+    result equals the separate fold and convolution passes bit for bit."""
+    import os
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    _, f = make_image(77, 48, 40, 5, 3, 0.1)
+    img = torch.tensor(f, dtype=torch.float32, device="cuda")
+    F = nld.features_from_image(img, 2)
+    wins = nld.window_table(2)
+    sig = [0.1, 0.15, 0.08, 0.2, 0.1, 0.12, 0.1, 0.3, 0.1]
+    v = torch.tensor(random_vector(8, F.shape[1]), dtype=torch.float32, device="cuda")
+    fused = nld.Plan(F, wins, sig, [1.0] * 9, bandwidth=bandwidth, cutoff=4)
+    os.environ["NLD_NO_PLANE"] = "1"
+    try:
+        plain = nld.Plan(F, wins, sig, [1.0] * 9, bandwidth=bandwidth, cutoff=4)
+    finally:
+        os.environ.pop("NLD_NO_PLANE", None)
+    assert torch.equal(fused.laplacian_matvec(v), plain.laplacian_matvec(v))
+    assert torch.equal(fused.anova_matvec(v), plain.anova_matvec(v))
+    fused.close()
+    plain.close()
