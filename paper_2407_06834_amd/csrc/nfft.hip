@@ -70,6 +70,17 @@ __device__ __forceinline__ double lane_bcast(double v, int q) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Value of v in the lane whose index is byte_addr / 4 (ds_bpermute; no LDS storage is used)
+__device__ __forceinline__ float lane_fetch(float v, int byte_addr) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_fetch(double v, int byte_addr) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(byte_addr, (int)(bits & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_ds_bpermute(byte_addr, (int)(bits >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Weights of the W = 2m taps of one node in one dimension (tap i at cell floor(u) - m + 1 + i,
 // distance fr + m - 1 - i): the per-tap window polynomials evaluated at x = 2 fr - 1.
 template <typename T, int W, typename P>
@@ -112,7 +123,6 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   constexpr int PAIRS = (TD == 1) ? W : W * W;
   constexpr int NP = (PAIRS + 63) / 64;
   constexpr int NI0 = (TD == 3) ? W : 1;
-  constexpr bool REG = (NP * K * 2 * (int)sizeof(T) / 4) <= 72;
   // fixed-point accumulators: 32-bit for FP32 data (resolution 2^-29 of the chunk's sum of
   // |v|, far below FP32 rounding of the result), 64-bit for FP64 data (2^-61)
   using Acc = typename std::conditional<sizeof(T) == 4, unsigned int, unsigned long long>::type;
@@ -121,15 +131,12 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   extern __shared__ unsigned char smem_raw[];
   Acc* acc = reinterpret_cast<Acc*>(smem_raw);
   __shared__ double s_part[kSpreadWaves];
-  __shared__ T s_psi[REG ? 1 : W * K];
   const int pe1 = w.pe[1], pe2 = w.pe[2];
   const int cells = w.pe[0] * pe1 * pe2;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
   GlobalPtr<T> psi = (GlobalPtr<T>)w.psi;
   for (int c = threadIdx.x; c < cells; c += kSpreadThreads) acc[c] = (Acc)0;
-  if constexpr (!REG)
-    for (int c = threadIdx.x; c < W * K; c += kSpreadThreads) s_psi[c] = psi[c];
   // fixed-point scale of this chunk
   double sa = 0.0;
   for (int p = job.pbeg + threadIdx.x; p < job.pend; p += kSpreadThreads)
@@ -148,10 +155,17 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   const int e = max(ilogb(tot), -90);
   const double scale = ldexp(1.0, kFix - e);
   const T scale_t = (T)scale;
-  // this lane's tap pairs and their window polynomials
-  int i1[NP], i2[NP];
+  // Tap weights: lanes [0, W) evaluate the window polynomial of the first kept dimension's taps,
+  // [W, 2W) the second's, [2W, 3W) the third's (one polynomial per lane and node); the lane that
+  // owns tap pair (i1, i2) of the last two dimensions fetches its two factors with ds_bpermute,
+  // and the first dimension's W weights are broadcast to every lane.
+  static_assert(TD * W <= 64, "one lane per tap and dimension");
+  const int my_tap = lane % W, my_dim = lane / W;   // lanes with my_dim >= TD idle here
+  T cf[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) cf[q] = psi[my_tap * K + q];
+  int i1[NP], i2[NP], src1[NP], src2[NP];
   bool pv[NP];
-  T c1[REG ? NP : 1][REG ? K : 1], c2[REG ? NP : 1][REG ? K : 1], c0[K];
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     const int t = lane + 64 * k;
@@ -159,19 +173,9 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     const int tt = pv[k] ? t : 0;
     i1[k] = (TD == 1) ? 0 : tt / W;
     i2[k] = (TD == 1) ? tt : tt % W;
-    if constexpr (REG) {
-#pragma unroll
-      for (int q = 0; q < K; ++q) {
-        c2[k][q] = psi[i2[k] * K + q];
-        c1[k][q] = (TD >= 2) ? psi[i1[k] * K + q] : (T)0;
-      }
-    }
+    src2[k] = ((TD - 1) * W + i2[k]) * 4;              // byte addresses of the source lanes
+    src1[k] = (TD >= 2) ? ((TD - 2) * W + i1[k]) * 4 : 0;
   }
-  if constexpr (TD == 3) {
-#pragma unroll
-    for (int q = 0; q < K; ++q) c0[q] = psi[(lane % W) * K + q];
-  }
-  if constexpr (!REG) __syncthreads();
   const int o0 = tile_origin(w, job.tile, 0), o1 = tile_origin(w, job.tile, 1),
             o2 = tile_origin(w, job.tile, 2);
   T accr[NP][NI0];
@@ -228,27 +232,28 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
         cur = bq;
       }
       const T vq = lane_bcast(vv, q);
-      const T x2 = (T)2 * lane_bcast(f2, q) - (T)1;
-      const T x1 = (T)2 * lane_bcast(f1, q) - (T)1;
+      T fsel;
+      if constexpr (TD == 3) {
+        const T fa = lane_bcast(f0, q), fb = lane_bcast(f1, q), fc = lane_bcast(f2, q);
+        fsel = (my_dim == 0) ? fa : (my_dim == 1) ? fb : fc;
+      } else if constexpr (TD == 2) {
+        const T fb = lane_bcast(f1, q), fc = lane_bcast(f2, q);
+        fsel = (my_dim == 0) ? fb : fc;
+      } else {
+        fsel = lane_bcast(f2, q);
+      }
+      const T wv = horner<T, K>(cf, (T)2 * fsel - (T)1);
       T w12[NP];
 #pragma unroll
       for (int k = 0; k < NP; ++k) {
-        T a2, a1 = (T)1;
-        if constexpr (REG) {
-          a2 = horner<T, K>(c2[k], x2);
-          if constexpr (TD >= 2) a1 = horner<T, K>(c1[k], x1);
-        } else {
-          a2 = horner<T, K>(s_psi + i2[k] * K, x2);
-          if constexpr (TD >= 2) a1 = horner<T, K>(s_psi + i1[k] * K, x1);
-        }
+        const T a2 = lane_fetch(wv, src2[k]);
+        const T a1 = (TD >= 2) ? lane_fetch(wv, src1[k]) : (T)1;
         w12[k] = vq * a1 * a2;
       }
       if constexpr (TD == 3) {
-        const T x0 = (T)2 * lane_bcast(f0, q) - (T)1;
-        const T p0 = horner<T, K>(c0, x0);          // tap (lane % W) of the first dimension
-        T s0[W];
+        T s0[W];                                      // lanes [0, W) hold the first dimension's taps
 #pragma unroll
-        for (int i = 0; i < W; ++i) s0[i] = lane_bcast(p0, i);
+        for (int i = 0; i < W; ++i) s0[i] = lane_bcast(wv, i);
 #pragma unroll
         for (int i = 0; i < W; ++i)
 #pragma unroll
