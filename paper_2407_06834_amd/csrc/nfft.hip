@@ -396,6 +396,92 @@ k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int 
     g[((long long)(o0 + x0) * w.n[1] + (o1 + x1)) * w.n[2] + (o2 + x2)] = acc[x0];
 }
 
+// Fold of a 3-D window with 8^3 tiles and cutoff M known at compile time: the same neighbour
+// and slot order as k_fold3 (so the same sums bit for bit), with every neighbour's overlap along
+// the first dimension fixed at compile time and the slot tables read up front, so that the
+// loads of all neighbours can be in flight together.
+template <typename T, int M>
+__global__ void __launch_bounds__(64)
+k_fold3m(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int job0,
+         const ImgDev* __restrict__ imgs, int check) {
+  constexpr int TS = 8, LEFT = M - 1, PE = TS + 2 * M - 1;
+  const Fold3Job job = jobs[job0 + blockIdx.x];
+  const WinDev& w = wins[job.win];
+  if (check && imgs[w.img].st->done) return;
+  GlobalPtr<T> padded = (GlobalPtr<T>)w.padded;
+  const long long slot_stride = w.slot_stride;
+  ConstPtr<int> tile_slot0 = (ConstPtr<int>)w.tile_slot0;
+  ConstPtr<int> tile_nslot = (ConstPtr<int>)w.tile_nslot;
+  const int x2 = threadIdx.x % TS, x1 = threadIdx.x / TS;
+  const int tc2 = job.tile & (w.nts[2] - 1);
+  const int tc1 = (job.tile >> w.lnts[2]) & (w.nts[1] - 1);
+  const int tc0 = job.tile >> (w.lnts[2] + w.lnts[1]);
+  // slot tables of the 27 neighbours (uniform)
+  int ns[27], s0t[27];
+#pragma unroll
+  for (int n = 0; n < 27; ++n) {
+    const int d0 = n / 9 - 1, d1 = (n / 3) % 3 - 1, d2 = n % 3 - 1;
+    const int t0 = (tc0 + d0) & (w.nts[0] - 1), t1 = (tc1 + d1) & (w.nts[1] - 1),
+              t2 = (tc2 + d2) & (w.nts[2] - 1);
+    const int gt = w.tile_off + (((t0 << w.lnts[1]) + t1) << w.lnts[2]) + t2;
+    ns[n] = tile_nslot[gt];
+    s0t[n] = tile_slot0[gt];
+  }
+  T acc[TS];
+#pragma unroll
+  for (int k = 0; k < TS; ++k) acc[k] = (T)0;
+  bool multi = false;
+#pragma unroll
+  for (int n = 0; n < 27; ++n) multi = multi || ns[n] > 1;
+  if (!multi) {
+    // at most one slot per neighbour: empty neighbours skipped (uniform branch), the others read
+    // without lane-dependent branches (address clamped into the neighbour's slot, value masked)
+#pragma unroll
+    for (int n = 0; n < 27; ++n) {
+      const int d0 = n / 9 - 1, d1 = (n / 3) % 3 - 1, d2 = n % 3 - 1;
+      const int s0 = d0 * TS - LEFT, s1 = d1 * TS - LEFT, s2 = d2 * TS - LEFT;
+      const int lo0 = s0 > 0 ? s0 : 0, hi0 = (s0 + PE < TS) ? s0 + PE : TS;
+      if (lo0 >= hi0) continue;                               // compile-time
+      if ((s1 > 0 ? s1 : 0) >= ((s1 + PE < TS) ? s1 + PE : TS)) continue;
+      if ((s2 > 0 ? s2 : 0) >= ((s2 + PE < TS) ? s2 + PE : TS)) continue;
+      if (ns[n] == 0) continue;                               // uniform: empty neighbour tile
+      const int p1 = x1 - s1, p2 = x2 - s2;
+      const bool ok = p1 >= 0 && p1 < PE && p2 >= 0 && p2 < PE;
+      const long long base = (long long)s0t[n] * slot_stride + (ok ? p1 * PE + p2 : 0);
+#pragma unroll
+      for (int x0 = 0; x0 < TS; ++x0) {
+        if (x0 < lo0 || x0 >= hi0) continue;                  // compile-time
+        const T val = padded[base + (long long)(x0 - s0) * PE * PE];
+        acc[x0] += ok ? val : (T)0;
+      }
+    }
+  } else {
+    for (int n = 0; n < 27; ++n) {
+      const int d0 = n / 9 - 1, d1 = (n / 3) % 3 - 1, d2 = n % 3 - 1;
+      const int s0 = d0 * TS - LEFT, s1 = d1 * TS - LEFT, s2 = d2 * TS - LEFT;
+      const int lo0 = s0 > 0 ? s0 : 0, hi0 = (s0 + PE < TS) ? s0 + PE : TS;
+      if (lo0 >= hi0) continue;
+      if ((s1 > 0 ? s1 : 0) >= ((s1 + PE < TS) ? s1 + PE : TS)) continue;
+      if ((s2 > 0 ? s2 : 0) >= ((s2 + PE < TS) ? s2 + PE : TS)) continue;
+      if (ns[n] == 0) continue;
+      const int p1 = x1 - s1, p2 = x2 - s2;
+      if (p1 < 0 || p1 >= PE || p2 < 0 || p2 >= PE) continue;
+      const auto src = padded + (long long)s0t[n] * slot_stride + p1 * PE + p2;
+      for (int x0 = lo0; x0 < hi0; ++x0) {
+        const auto q = src + (long long)(x0 - s0) * PE * PE;
+        T sum = (T)0;
+        for (int k = 0; k < ns[n]; ++k) sum += q[(long long)k * slot_stride];
+        acc[x0] += sum;
+      }
+    }
+  }
+  T __attribute__((address_space(1)))* g = (T __attribute__((address_space(1)))*)w.grid + w.grid_off;
+  const int o0 = tc0 * TS, o1 = tc1 * TS, o2 = tc2 * TS;
+#pragma unroll
+  for (int x0 = 0; x0 < TS; ++x0)
+    g[((long long)(o0 + x0) * w.n[1] + (o1 + x1)) * w.n[2] + (o2 + x2)] = acc[x0];
+}
+
 // ---------------------------------------------------------------------------- convolution
 // Per dimension, every grid line is circularly convolved with the window's real even kernel
 // (multiplication of its DFT by the Fourier multiplier).  Two real lines are packed as one
@@ -1030,9 +1116,13 @@ void spread_fold(const LaunchSet& ls, VecArg in, int check, hipStream_t s) {
   }
   tiles_dispatch<T>(ls, in, check, s, false);
   const int n8 = ls.f3_begin[1] - ls.f3_begin[0], n16 = ls.f3_begin[2] - ls.f3_begin[1];
-  if (n8 > 0)
-    hipLaunchKernelGGL((k_fold3<T, 8>), dim3(n8), dim3(64), 0, s, ls.d_wins, ls.d_f3jobs,
-                       ls.f3_begin[0], ls.d_imgs, check);
+  if (n8 > 0) {
+    auto k = (ls.m == 1) ? k_fold3m<T, 1> : (ls.m == 2) ? k_fold3m<T, 2> : (ls.m == 3) ? k_fold3m<T, 3>
+           : (ls.m == 4) ? k_fold3m<T, 4> : (ls.m == 5) ? k_fold3m<T, 5> : (ls.m == 6) ? k_fold3m<T, 6>
+           : (ls.m == 7) ? k_fold3m<T, 7> : k_fold3m<T, 8>;
+    hipLaunchKernelGGL(k, dim3(n8), dim3(64), 0, s, ls.d_wins, ls.d_f3jobs, ls.f3_begin[0],
+                       ls.d_imgs, check);
+  }
   if (n16 > 0)
     hipLaunchKernelGGL((k_fold3<T, 16>), dim3(n16), dim3(256), 0, s, ls.d_wins, ls.d_f3jobs,
                        ls.f3_begin[1], ls.d_imgs, check);
