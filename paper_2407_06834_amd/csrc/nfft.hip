@@ -98,10 +98,11 @@ __device__ __forceinline__ void poly_row(P psi, T fr, T* wt) {
 // last two kept dimensions and keeps the 2m taps of the first kept dimension in registers, so a
 // run of r nodes costs one set of LDS additions instead of r.  When the cell changes the
 // registers are added into the padded tile (tile plus the 2m - 1 halo cells the taps reach) as
-// fixed-point integers scaled by 2^(29 - e) in 32 bits (FP32 data) or 2^(61 - e) in 64 bits (FP64
-// data), 2^e <= sum |v| over the chunk: integer addition is exact and associative, so the result
-// does not depend on the order in which the wavefronts add (reproducible), and ds_add_u32 /
-// ds_add_u64 are fast where LDS float atomics are not.
+// fixed-point integers (2^e <= sum |v| over the chunk; FP32 data: a 32-bit word scaled by
+// 2^(29 - e) plus a 32-bit remainder word 2^20 finer, FP64 data: one 64-bit word scaled by
+// 2^(61 - e)): integer addition is exact and associative, so the result does not depend on the
+// order in which the wavefronts add (reproducible), and ds_add_u32 / ds_add_u64 are fast where
+// LDS float atomics are not.
 // The slot is then written back in the working precision; the fold kernel sums the slots that
 // cover each grid cell.
 template <typename T, int W, int TD>
@@ -123,20 +124,29 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   constexpr int PAIRS = (TD == 1) ? W : W * W;
   constexpr int NP = (PAIRS + 63) / 64;
   constexpr int NI0 = (TD == 3) ? W : 1;
-  // fixed-point accumulators: 32-bit for FP32 data (resolution 2^-29 of the chunk's sum of
-  // |v|, far below FP32 rounding of the result), 64-bit for FP64 data (2^-61)
+  // Fixed-point accumulators with scale 2^(kFix - e), 2^e <= sum |v| over the chunk.  FP64
+  // data: one 64-bit word (resolution 2^-61 of sum |v|).  FP32 data: two 32-bit words per
+  // cell, the rounded value and its remainder in units of 2^-20 (resolution 2^-49 of sum |v|),
+  // so that the spreading stays far more accurate than FP32 rounding of the result (the
+  // product then stays symmetric to working precision, which CG in FP32 needs).
   using Acc = typename std::conditional<sizeof(T) == 4, unsigned int, unsigned long long>::type;
   using SAcc = typename std::conditional<sizeof(T) == 4, int, long long>::type;
   constexpr int kFix = sizeof(T) == 4 ? 29 : 61;
+  constexpr bool kTwo = sizeof(T) == 4;
+  constexpr float kLoScale = 1048576.0f;                 // 2^20
   extern __shared__ unsigned char smem_raw[];
   Acc* acc = reinterpret_cast<Acc*>(smem_raw);
+  Acc* acc_lo = acc + (kTwo ? w.pe[0] * w.pe[1] * w.pe[2] : 0);
   __shared__ double s_part[kSpreadWaves];
   const int pe1 = w.pe[1], pe2 = w.pe[2];
   const int cells = w.pe[0] * pe1 * pe2;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
   GlobalPtr<T> psi = (GlobalPtr<T>)w.psi;
-  for (int c = threadIdx.x; c < cells; c += kSpreadThreads) acc[c] = (Acc)0;
+  for (int c = threadIdx.x; c < cells; c += kSpreadThreads) {
+    acc[c] = (Acc)0;
+    if constexpr (kTwo) acc_lo[c] = (Acc)0;
+  }
   // fixed-point scale of this chunk
   double sa = 0.0;
   for (int p = job.pbeg + threadIdx.x; p < job.pend; p += kSpreadThreads)
@@ -205,10 +215,15 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
       const int b = cbase + loff[k];
 #pragma unroll
       for (int i = 0; i < NI0; ++i) {
-        SAcc qv;
-        if constexpr (sizeof(T) == 4) qv = __float2int_rn(accr[k][i]);
-        else qv = __double2ll_rn(accr[k][i]);
-        atomicAdd(&acc[b + i * s01], (Acc)qv);
+        if constexpr (kTwo) {
+          const float x = accr[k][i];
+          const float hf = rintf(x);
+          const int lo = __float2int_rn((x - hf) * kLoScale);   // x - hf is exact, |.| <= 1/2
+          atomicAdd(&acc[b + i * s01], (Acc)(int)hf);
+          atomicAdd(&acc_lo[b + i * s01], (Acc)lo);
+        } else {
+          atomicAdd(&acc[b + i * s01], (Acc)__double2ll_rn(accr[k][i]));
+        }
         accr[k][i] = (T)0;
       }
     }
@@ -267,8 +282,11 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   if (cur != kNone) flush();
   __syncthreads();
   const double inv = 1.0 / scale;
-  for (int c = threadIdx.x; c < cells; c += kSpreadThreads)
-    out[c] = (T)((double)(SAcc)acc[c] * inv);
+  for (int c = threadIdx.x; c < cells; c += kSpreadThreads) {
+    double val = (double)(SAcc)acc[c];
+    if constexpr (kTwo) val += (double)(SAcc)acc_lo[c] * (1.0 / (double)kLoScale);
+    out[c] = (T)(val * inv);
+  }
 }
 
 // Fold: every grid cell sums, in fixed order, the padded-tile slots that cover it.  Along each
@@ -1031,8 +1049,9 @@ int gather_stage_min() {
 
 template <typename T, int W>
 void launch_tiles(const LaunchSet& ls, VecArg in, int check, hipStream_t s, bool gather) {
-  // spreading accumulates in 32-bit (FP32) or 64-bit (FP64) fixed point: sizeof(T) per cell
-  const size_t lds = (size_t)ls.max_padded * sizeof(T);
+  // spreading accumulates in fixed point: two 32-bit words (FP32) or one 64-bit word (FP64) per
+  // cell; gathering stages the tile in T
+  const size_t lds = (size_t)ls.max_padded * (gather ? sizeof(T) : 8);
   for (int g = 0; g < 3; ++g) {
     const int j0 = ls.tjob_begin[g], nj = ls.tjob_begin[g + 1] - j0;
     if (nj == 0) continue;

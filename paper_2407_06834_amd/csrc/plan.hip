@@ -622,14 +622,14 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     // tiles: the padded tile (tile + 2m - 1 halo cells per dimension) must fit in LDS
     int tsz;
     if (t == 3) {
-      // the spreading accumulates the padded tile in fixed point of the data's width
+      // the spreading accumulates the padded tile in 8 bytes of fixed point per cell
       // 8^3 tiles: smaller padded tiles in LDS give more resident workgroups, which measured
       // faster than 16^3 tiles on the 512^2 workload despite the larger halo overhead
       tsz = P.tile3 ? P.tile3 : 8;
       if (P.tile3 == 0)
         if (const char* e = std::getenv("NLD_TILE3")) tsz = std::atoi(e);
       if (tsz != 8 && tsz != 16) tsz = 8;
-      if ((long long)std::pow(tsz + 2 * m - 1, 3) * P.elem > P.lds_limit) tsz = 8;
+      if ((long long)std::pow(tsz + 2 * m - 1, 3) * 8LL > P.lds_limit) tsz = 8;
     } else if (t == 2) {
       tsz = std::min(64, n);
     } else {
@@ -650,7 +650,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
         throw std::invalid_argument("tile sizes must be powers of two");
       padded *= w.pe[dd];
     }
-    if (padded * (long long)P.elem > P.lds_limit)
+    if (padded * 8LL > P.lds_limit)
       throw std::invalid_argument("padded tile does not fit in LDS");
     if ((long long)w.ts[0] * w.ts[1] * w.ts[2] > (1LL << kCellBits))
       throw std::invalid_argument("tile too large for the sort key");
