@@ -11,6 +11,12 @@ Laplacian product inside CG, timed with HIP events by the library on the solve's
 and a CPU baseline (the FP64 NFFT oracle, one product timed on the host, extrapolated).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64] [--no-cpu-baseline]
+                    [--profile-copy]
+
+`roofline.traffic` is the HBM traffic of one product measured with rocprofv3 counters
+(FETCH_SIZE and WRITE_SIZE summed over the product's kernels, each scaled by what the counter
+reads for a device copy of 256 MiB; --profile-copy runs that copy after the timed steps); it is
+reported only while the kernel sources hash to the value recorded with the measurement.
 """
 from __future__ import annotations
 
@@ -24,6 +30,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes of one FP32 Laplacian product on this workload, from the rocprofv3 counter runs kept
+# in profiles/nfft_laplacian_512_fp32_hbm_traffic.md, valid for the kernel sources of that hash
+TRAFFIC = {"sha1": "a1addf1e69dcfe7980b8df702ec92b527881204f", "bytes": 1351510014}
+KERNEL_SOURCES = ("paper_2407_06834_amd/csrc/nfft.hip", "paper_2407_06834_amd/csrc/plan.hip",
+                  "paper_2407_06834_amd/csrc/nld_internal.h", "paper_2407_06834_amd/csrc/nld_device.h")
+
+
+def kernel_sha1() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 N1 = N2 = 512
 RHO = 2
 SIGMAS = (0.05, 0.1, 0.2)
@@ -48,6 +69,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dtype", choices=("f32", "f64"), default="f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -94,6 +116,12 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
+    if args.profile_copy:
+        a = torch.ones(64 * 1024 * 1024, device=dev)   # 256 MiB, the counters' scale reference
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     mpix = 9 * N / (ms_step * 1e-3) / 1e6
     bad = [i for i in infos if i[2]["status"] != "OK"]
 
@@ -135,7 +163,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": (round(TRAFFIC["bytes"] / 1e9, 4)
+                        if TRAFFIC["sha1"] is not None and TRAFFIC["sha1"] == kernel_sha1() and
+                        args.dtype == "f32" else None),
+            "traffic_unit": "GB per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "bytes_per_launch": bytes_mv,
             "ms_per_launch": round(ms_mv, 4),
         },
