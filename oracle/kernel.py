@@ -6,6 +6,13 @@ Plain definitions, FP64:
   D = W 1,   L = diag(D) - W   (graph Laplacian; its diagonal does not depend on W_ii)
   eta = D - sum_l w_l          (degree with the zero-diagonal convention of the paper)
   A = I + alpha L              (the system (lambda I + mu L) u = lambda f with alpha = mu/lambda)
+
+Diagonal preconditioners of Sec. 4.3.1 in the alpha form (lambda = 1, mu = alpha):
+  P_a = I + alpha diag(eta)                                   (Jacobi)
+  P_b = diag( (sum_j a_ij^2)^(1/2) )                          (row 2-norms of A)
+  P_b' = [ alpha^2 sum_l w_l^2 diag(Gamma_l o Gamma_l 1) + P_a^2 ]^(1/2)
+where Gamma_l is K_l with a zero diagonal; P_b' keeps only the L squared window terms of the
+square of the window sum (the cross terms are dropped, as the paper does for ANOVA kernels).
 """
 from __future__ import annotations
 
@@ -68,3 +75,27 @@ def anova_rows_direct(F, wins, sigmas, weights, rows, v, chunk: int = 256) -> np
 def anova_matvec_direct(F, wins, sigmas, weights, v, chunk: int = 256) -> np.ndarray:
     """Full W v by direct summation (O(N^2 L)); for small N."""
     return anova_rows_direct(F, wins, sigmas, weights, np.arange(F.shape[1]), v, chunk)
+
+
+def l2_window_degree(F, wins, sigmas, weights) -> np.ndarray:
+    """sum_l w_l^2 (Gamma_l o Gamma_l) 1: squared kernel entries, zero diagonal."""
+    N = F.shape[1]
+    out = np.zeros(N)
+    for win, s, w in zip(wins, sigmas, weights):
+        K = window_kernel_dense(F, win, s)
+        out += w * w * ((K * K).sum(axis=1) - 1.0)
+    return out
+
+
+def precond_jacobi(eta: np.ndarray, alpha: float) -> np.ndarray:
+    return 1.0 + alpha * eta
+
+
+def precond_l2_anova(eta: np.ndarray, d2: np.ndarray, alpha: float) -> np.ndarray:
+    """P_b' from eta and d2 = sum_l w_l^2 (Gamma_l o Gamma_l) 1."""
+    return np.sqrt(alpha * alpha * d2 + (1.0 + alpha * eta) ** 2)
+
+
+def precond_l2_full(A: np.ndarray) -> np.ndarray:
+    """P_b: the 2-norms of the rows of A."""
+    return np.sqrt((A * A).sum(axis=1))

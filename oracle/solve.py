@@ -139,14 +139,15 @@ def pcg_ubasis(apply_A, f, eta, alpha, tol, maxit, u0=None, record=False):
     return u, it, relres, (hist if record else None)
 
 
-def pcg_projector(apply_A, f, eta, alpha, tol, maxit, u0=None, record=False):
-    """Deflated Jacobi PCG with the projector Pi = I - 1 1^T/N in the original basis:
-    ubar = mean(f), z0 = Pi u0, s = Pi(r / P), u = ubar 1 + z.  A constant f (f_perp = 0)
-    returns u = f with no iteration."""
+def pcg_projector(apply_A, f, eta, alpha, tol, maxit, u0=None, record=False, P=None):
+    """Deflated diagonally preconditioned CG with the projector Pi = I - 1 1^T/N in the original
+    basis: ubar = mean(f), z0 = Pi u0, s = Pi(r / P), u = ubar 1 + z.  P defaults to the Jacobi
+    diagonal 1 + alpha eta (P_{U,a}); passing the l2 diagonal gives P_{U,b}.  A constant f
+    (f_perp = 0) returns u = f with no iteration."""
     if np.all(f == f[0]):
         return f.copy(), 0, 0.0, ([] if record else None)
     u0 = f if u0 is None else u0
-    P = 1.0 + alpha * eta
+    P = 1.0 + alpha * eta if P is None else P
     ubar = f.mean()
 
     def proj(x):
@@ -165,9 +166,10 @@ def cg_plain(apply_A, f, tol, maxit, u0=None):
     return u, it, relres
 
 
-def pcg_jacobi(apply_A, f, eta, alpha, tol, maxit, u0=None):
+def pcg_jacobi(apply_A, f, eta, alpha, tol, maxit, u0=None, P=None):
+    """Diagonally preconditioned CG without deflation (P_a by default, or a given diagonal)."""
     u0 = f if u0 is None else u0
-    P = 1.0 + alpha * eta
+    P = 1.0 + alpha * eta if P is None else P
     u, it, relres, _ = _pcg(apply_A, lambda r: r / P, f, u0, tol, maxit)
     return u, it, relres
 
