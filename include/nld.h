@@ -139,7 +139,10 @@ typedef struct {
   double tol;        /* stop when ||r_k||_2 <= tol * ||f - mean(f)||_2 (recursive residual) */
   int32_t maxit;     /* maximum number of iterations (operator applications)              */
   int32_t use_u0;    /* 1: u holds the initial guess on entry; 0: start from f (Sec. 5.3)  */
-  int32_t precond;   /* 1: Jacobi preconditioner P = I + alpha diag(eta); 0: none          */
+  int32_t precond;   /* 0: none; 1: Jacobi P_a = I + alpha diag(eta); 2: the l2 diagonal   */
+                     /* P_b' = (alpha^2 sum_l w_l^2 diag(Gamma_l o Gamma_l 1) + P_a^2)^(1/2) */
+                     /* of Sec. 4.3.1 (squared kernels = Gaussians of width sigma_l / sqrt 2, */
+                     /* summed once per plan on the plan's grids; Gamma_l: K_l, zero diagonal) */
   int32_t deflate;   /* 1: change of basis removing the eigenvector 1 (Sec. 4.2, 5.4)      */
   int32_t true_residual; /* 1: also compute the true residual at exit (one more matvec)     */
   int32_t timing;    /* 1: time every operator application with HIP events on the stream s   */

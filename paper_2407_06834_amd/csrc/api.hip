@@ -226,9 +226,10 @@ nld_status pcg_solve(nfft_plan_t plan, double alpha, const void* f, void* u,
   if (!finite_pos(alpha)) return fail(NLD_E_INVAL, "pcg_solve: alpha must be finite and > 0");
   if (!finite_pos(opts->tol) || opts->tol >= 1.0) return fail(NLD_E_INVAL, "pcg_solve: tol must be in (0, 1)");
   if (opts->maxit < 0) return fail(NLD_E_INVAL, "pcg_solve: maxit must be >= 0");
-  if ((opts->precond != 0 && opts->precond != 1) || (opts->deflate != 0 && opts->deflate != 1) ||
-      (opts->use_u0 != 0 && opts->use_u0 != 1))
-    return fail(NLD_E_INVAL, "pcg_solve: precond, deflate and use_u0 must be 0 or 1");
+  if (opts->precond < 0 || opts->precond > 2)
+    return fail(NLD_E_INVAL, "pcg_solve: precond must be 0, 1 or 2");
+  if ((opts->deflate != 0 && opts->deflate != 1) || (opts->use_u0 != 0 && opts->use_u0 != 1))
+    return fail(NLD_E_INVAL, "pcg_solve: deflate and use_u0 must be 0 or 1");
   std::memset(info, 0, sizeof(*info));
   info->relres_true = -1.0;
   nld_status result = NLD_OK;
@@ -254,9 +255,10 @@ nld_status pcg_solve_batched(const nfft_plan_t* plans, const double* alpha, cons
   if (count < 1 || count > 65536) return fail(NLD_E_INVAL, "pcg_solve_batched: count must be in [1, 65536]");
   if (!finite_pos(opts->tol) || opts->tol >= 1.0) return fail(NLD_E_INVAL, "pcg_solve_batched: tol must be in (0, 1)");
   if (opts->maxit < 0) return fail(NLD_E_INVAL, "pcg_solve_batched: maxit must be >= 0");
-  if ((opts->precond != 0 && opts->precond != 1) || (opts->deflate != 0 && opts->deflate != 1) ||
-      (opts->use_u0 != 0 && opts->use_u0 != 1))
-    return fail(NLD_E_INVAL, "pcg_solve_batched: precond, deflate and use_u0 must be 0 or 1");
+  if (opts->precond < 0 || opts->precond > 2)
+    return fail(NLD_E_INVAL, "pcg_solve_batched: precond must be 0, 1 or 2");
+  if ((opts->deflate != 0 && opts->deflate != 1) || (opts->use_u0 != 0 && opts->use_u0 != 1))
+    return fail(NLD_E_INVAL, "pcg_solve_batched: deflate and use_u0 must be 0 or 1");
   std::vector<nld::Plan*> P(count);
   for (int b = 0; b < count; ++b) {
     if (!plans[b] || !f[b] || !u[b]) return fail(NLD_E_INVAL, "pcg_solve_batched: null plan or vector");
@@ -297,9 +299,10 @@ nld_status adjoint_solve(nfft_plan_t plan, double alpha, const void* f, const vo
   if (!finite_pos(alpha)) return fail(NLD_E_INVAL, "adjoint_solve: alpha must be finite and > 0");
   if (!finite_pos(opts->tol) || opts->tol >= 1.0) return fail(NLD_E_INVAL, "adjoint_solve: tol must be in (0, 1)");
   if (opts->maxit < 0) return fail(NLD_E_INVAL, "adjoint_solve: maxit must be >= 0");
-  if ((opts->precond != 0 && opts->precond != 1) || (opts->deflate != 0 && opts->deflate != 1) ||
-      (opts->use_u0 != 0 && opts->use_u0 != 1))
-    return fail(NLD_E_INVAL, "adjoint_solve: precond, deflate and use_u0 must be 0 or 1");
+  if (opts->precond < 0 || opts->precond > 2)
+    return fail(NLD_E_INVAL, "adjoint_solve: precond must be 0, 1 or 2");
+  if ((opts->deflate != 0 && opts->deflate != 1) || (opts->use_u0 != 0 && opts->use_u0 != 1))
+    return fail(NLD_E_INVAL, "adjoint_solve: deflate and use_u0 must be 0 or 1");
   std::memset(info, 0, sizeof(*info));
   info->relres_true = -1.0;
   nld_status result = NLD_OK;

@@ -72,6 +72,7 @@ struct ImgDev {
   int nred;            // blocks of the image's FP64 reductions
   void* vec[kNumVec];  // CG vectors z, r, p, q, right-hand side f, solution u, ones
   double* D;           // degree vector
+  double* D2;          // sum_l w_l^2 K_l(sigma_l / sqrt 2) 1 (l2 preconditioner), or null
   double* sumv;        // sum of the input (windows without kept dimensions)
   CgState* st;
   double* red;         // reduction partials [nred][8]
@@ -121,6 +122,7 @@ struct CgState {
   double const_f;      // 0 if f is constant
   double last_pq, last_rho;  // last <p, A p> and <r, s> (diagnostics)
   double sum_pinv;     // sum_i 1 / P_i
+  double w2sum;        // sum_l w_l^2 (self terms of D2)
   int iters, maxit, done, status, precond, deflate;
   unsigned int ticket[8];
 };
@@ -204,6 +206,12 @@ struct Plan {
   double* sumv = nullptr;          // sum of the vector (windows without kept dimensions)
   bool has_flat = false;           // some window has no kept dimension: K_l = 1 1^T
   bool have_D = false;
+  // l2 preconditioner (Sec. 4.3.1): multiplier tables of the kernels exp(-r^2 / (sigma_l^2 / 2))
+  // on the same grids, window descriptors with weights w_l^2, and D2 (built on first use)
+  void* coef_b = nullptr;
+  WinDev* d_wins_b = nullptr;
+  double* D2 = nullptr;
+  bool have_D2 = false;
   double max_eta = 0.0;            // max(D) - sum_l w_l
   void* ones = nullptr;            // vector of ones (precision T)
   // schedules: tile jobs grouped by window dimension t (group g holds the jobs of t = g + 1)
@@ -272,6 +280,8 @@ void gradient_sums(Plan& P, const void* p, const void* u, std::vector<double>& o
 // CG (pcg.hip)
 void compute_max_eta(Plan& P, hipStream_t s);
 void update_kernel(Plan& P, const double* sigma, const double* weight, hipStream_t s);
+// D2 = sum_l w_l^2 K_l(sigma_l / sqrt 2) 1 for the l2 preconditioner (plan.hip, lazily)
+void ensure_l2_degree(Plan& P, hipStream_t s);
 nld_status run_pcg(Plan& P, double alpha, const void* f, void* u, const nld_pcg_opts& o,
                    nld_pcg_info& info, hipStream_t s);
 nld_status run_adjoint(Plan& P, double alpha, const void* u, const void* g, void* p, double* grad,

@@ -23,9 +23,15 @@ namespace nld {
 
 namespace {
 
+// Inverse diagonal preconditioner: none (precond 0), Jacobi P_a = 1 + alpha eta (1), or the l2
+// diagonal P_b' = (alpha^2 (D2 - sum w_l^2) + P_a^2)^(1/2) of Sec. 4.3.1 (2).
 template <typename T>
-__device__ __forceinline__ double pinv(const CgState* st, const double* D, long long i) {
-  return st->precond ? 1.0 / (1.0 + st->alpha * (D[i] - st->wsum)) : 1.0;
+__device__ __forceinline__ double pinv(const CgState* st, const ImgDev& im, long long i) {
+  if (st->precond == 0) return 1.0;
+  const double pa = 1.0 + st->alpha * (im.D[i] - st->wsum);
+  if (st->precond == 1) return 1.0 / pa;
+  const double d2 = fmax(im.D2[i] - st->w2sum, 0.0);   // the off-diagonal sum, never negative
+  return 1.0 / sqrt(st->alpha * st->alpha * d2 + pa * pa);
 }
 
 // Every CG kernel runs one row of blocks per image (blockIdx.y); the reductions of an image use
@@ -46,7 +52,7 @@ k_cg_stats(const ImgDev* __restrict__ imgs, int u0sel) {
     s0 += (double)f[i];
     s1 += (double)u0[i];
     s2 += (f[i] != f0) ? 1.0 : 0.0;
-    s3 += pinv<T>(st, im.D, i);
+    s3 += pinv<T>(st, im, i);
   }
   const double vals[4] = {s0, s1, s2, s3};
   double tot[4];
@@ -114,13 +120,12 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_init2(const ImgDev* __restri
   CgState* st = im.st;
   if (st->done || blockIdx.x >= (unsigned)im.nred) return;
   const T* r = reinterpret_cast<const T*>(im.vec[V_R]);
-  const double* D = im.D;
   const long long N = im.N;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < N;
        i += (long long)im.nred * kRedThreads) {
     const double rv = (double)r[i];
-    const double t = rv * pinv<T>(st, D, i);
+    const double t = rv * pinv<T>(st, im, i);
     s[0] += rv * rv;
     s[1] += t;
     s[2] += rv * t;
@@ -141,7 +146,6 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_update(const ImgDev* __restr
   T* __restrict__ r = reinterpret_cast<T*>(im.vec[V_R]);
   const T* __restrict__ p = reinterpret_cast<const T*>(im.vec[V_P]);
   const T* __restrict__ q = reinterpret_cast<const T*>(im.vec[V_Q]);
-  const double* D = im.D;
   const long long N = im.N;
   const double a = st->a, mq = st->mean_q;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
@@ -151,7 +155,7 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_update(const ImgDev* __restr
     const T rt = (T)((double)r[i] - a * ((double)q[i] - mq));
     r[i] = rt;
     const double rv = (double)rt;
-    const double t = rv * pinv<T>(st, D, i);
+    const double t = rv * pinv<T>(st, im, i);
     s[0] += rv * rv;
     s[1] += t;
     s[2] += rv * t;
@@ -170,13 +174,12 @@ __global__ void k_cg_direction(const ImgDev* __restrict__ imgs, int first) {
   if (st->done) return;
   T* __restrict__ r = reinterpret_cast<T*>(im.vec[V_R]);
   T* __restrict__ p = reinterpret_cast<T*>(im.vec[V_P]);
-  const double* D = im.D;
   const double mt = st->mean_t, beta = st->beta, c = st->mean_r;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < im.N;
        i += (long long)gridDim.x * blockDim.x) {
     const double rv = (double)r[i] - c;
     r[i] = (T)rv;
-    const double s = rv * pinv<T>(st, D, i) - mt;
+    const double s = rv * pinv<T>(st, im, i) - mt;
     p[i] = (T)(first ? s : s + beta * (double)p[i]);
   }
 }
@@ -243,6 +246,7 @@ nld_status run_pcg_t(Plan& P, double alpha, const void* f, void* u, const nld_pc
   h->maxit = o.maxit;
   h->precond = o.precond;
   h->deflate = o.deflate;
+  for (double w : P.weight) h->w2sum += w * w;
   h->status = NLD_OK;
   NLD_HIP(hipMemcpyAsync(P.st, h, sizeof(CgState), hipMemcpyHostToDevice, s));
   P.img_host->vec[V_F] = const_cast<void*>(f);
@@ -386,6 +390,7 @@ nld_status run_adjoint(Plan& P, double alpha, const void* u, const void* g, void
 
 nld_status run_pcg(Plan& P, double alpha, const void* f, void* u, const nld_pcg_opts& o,
                    nld_pcg_info& info, hipStream_t s) {
+  if (o.precond == 2) ensure_l2_degree(P, s);
   if (!P.have_D) {
     matvec(P, P.ones, P.D, EPI_DEGREE, s);
     P.have_D = true;
@@ -429,6 +434,8 @@ template <typename T>
 nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void* const* f,
                              void* const* u, int count, const nld_pcg_opts& o, nld_pcg_info* infos,
                              hipStream_t s) {
+  if (o.precond == 2)
+    for (int b = 0; b < count; ++b) ensure_l2_degree(*plans[b], s);
   const auto t0 = std::chrono::steady_clock::now();
   hipStream_t cs = batch_stream();
   hipEvent_t ev_in, ev_out;
@@ -588,6 +595,7 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
       h.maxit = o.maxit;
       h.precond = o.precond;
       h.deflate = o.deflate;
+      for (double w : plans[b]->weight) h.w2sum += w * w;
       h.status = NLD_OK;
     }
     NLD_HIP(hipMemcpyAsync(d_st, sth, (size_t)count * sizeof(CgState), hipMemcpyHostToDevice, cs));

@@ -930,6 +930,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   im.vec[V_U] = nullptr;
   im.vec[V_ONES] = P.ones;
   im.D = P.D;
+  im.D2 = nullptr;
   im.sumv = P.sumv;
   im.st = P.st;
   im.red = P.red;
@@ -1041,6 +1042,56 @@ static void update_kernel_t(Plan& P, const double* sigma, const double* weight, 
   upload_windows<T>(P, wins_dv, s);
   NLD_HIP(hipStreamSynchronize(s));
   P.have_D = false;
+  P.have_D2 = false;
+}
+
+// Multiplier tables of exp(-r^2 / (sigma_l^2 / 2)) on the plan's grids (the squared kernels:
+// widths on the torus divided by sqrt 2, same bandwidth and window), descriptors with weights
+// w_l^2, and D2 = sum_l w_l^2 K_l(sigma_l / sqrt 2) 1 for the l2 preconditioner.  The coarser
+// truncation at the same bandwidth only affects the preconditioner, never the solution.
+template <typename T>
+static void ensure_l2_t(Plan& P, hipStream_t s) {
+  const int L = P.L, n_max = P.n_max;
+  std::vector<T> cb(3LL * n_max * L, (T)0);
+  for (int l = 0; l < L; ++l) {
+    const WinDev& w = P.wins[l];
+    const int n = P.info[l].grid, M = P.info[l].bandwidth;
+    for (int dd = 0; dd < 3; ++dd) {
+      if (w.n[dd] == 1) continue;
+      const double st = P.sig_t[3 * (size_t)l + dd] / std::sqrt(2.0);
+      for (int q = 0; q < n; ++q) {
+        const int kf = (q < n / 2) ? q : q - n;
+        if (std::abs(kf) <= M / 2 - 1) {
+          const double bh = std::sqrt(M_PI) * st * std::exp(-std::pow(M_PI * st * kf, 2));
+          const double ph = kb_fourier(kf, n, w.m, w.b);
+          cb[((size_t)l * 3 + dd) * n_max + q] = (T)(bh / (ph * ph));
+        }
+      }
+    }
+  }
+  if (!P.coef_b) P.coef_b = dalloc<T>((long long)cb.size(), s);
+  NLD_HIP(hipMemcpyAsync(P.coef_b, cb.data(), cb.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  std::vector<WinDev> wb(P.wins);
+  for (int l = 0; l < L; ++l) {
+    wb[l].coef = (const T*)P.coef_b + (size_t)l * 3 * n_max;
+    wb[l].weight = P.weight[l] * P.weight[l];
+  }
+  if (!P.d_wins_b) P.d_wins_b = dalloc<WinDev>(L, s);
+  NLD_HIP(hipMemcpyAsync(P.d_wins_b, wb.data(), L * sizeof(WinDev), hipMemcpyHostToDevice, s));
+  if (!P.D2) P.D2 = dalloc<double>(P.N, s);
+  LaunchSet lb = P.ls_unfused;
+  lb.d_wins = P.d_wins_b;
+  matvec_set(lb, VecArg{P.ones, V_ONES}, VecArg{nullptr, V_Q}, P.D2, EPI_DEGREE, s);
+  P.img_host->D2 = P.D2;
+  NLD_HIP(hipMemcpyAsync(P.d_img, P.img_host, sizeof(ImgDev), hipMemcpyHostToDevice, s));
+  NLD_HIP(hipStreamSynchronize(s));   // host staging above is released on return
+  P.have_D2 = true;
+}
+
+void ensure_l2_degree(Plan& P, hipStream_t s) {
+  if (P.have_D2) return;
+  if (P.prec == NLD_FP32) ensure_l2_t<float>(P, s);
+  else ensure_l2_t<double>(P, s);
 }
 
 void update_kernel(Plan& P, const double* sigma, const double* weight, hipStream_t s) {
@@ -1055,7 +1106,7 @@ void release_plan(Plan& P) {
                   P.d_conv[2], P.z, P.r, P.p, P.q, P.red, P.st, P.coef_dv, P.d_wins_dv[0],
                   P.d_wins_dv[1], P.d_wins_dv[2], P.grid_save, P.yk, P.yks, P.dl, P.dls,
                   P.adj_part, P.d_img, P.d_pjobs, P.d_f3jobs_u, P.d_conv_u[0], P.d_conv_u[1],
-                  P.d_conv_u[2]};
+                  P.d_conv_u[2], P.coef_b, P.d_wins_b, P.D2};
   for (void* b : bufs) dfree(b, s);
   (void)hipStreamSynchronize(s);
   if (P.img_host) (void)hipHostFree(P.img_host);

@@ -125,6 +125,13 @@ def _dtype(prec: int):
     return torch.float32 if prec == NLD_FP32 else torch.float64
 
 
+def _precond(p) -> int:
+    """Preconditioner code: False/'none' 0, True/'jacobi' 1 (P_a), 'l2' 2 (P_b')."""
+    if isinstance(p, str):
+        return {"none": 0, "jacobi": 1, "l2": 2}[p]
+    return int(p)
+
+
 def _vec(t: torch.Tensor, n: int, dtype, name: str):
     if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.numel() == n):
         raise ValueError(f"{name}: expected a contiguous {dtype} CUDA tensor with {n} elements")
@@ -243,7 +250,7 @@ class Plan:
         u = torch.empty_like(f) if out is None else out
         if u0 is not None:
             u.copy_(u0)
-        opts = PcgOpts(float(tol), int(maxit), 1 if u0 is not None else 0, int(bool(precond)),
+        opts = PcgOpts(float(tol), int(maxit), 1 if u0 is not None else 0, _precond(precond),
                        int(bool(deflate)), int(bool(true_residual)), int(bool(timing)))
         info = PcgInfo()
         st = load().pcg_solve(self.handle, float(alpha), _vec(f, self.N, self.dtype, "f"),
@@ -326,7 +333,7 @@ def pcg_solve_batched(plans, alphas, fs, us=None, tol: float = 1e-6, maxit: int 
     al = (ctypes.c_double * n)(*[float(a) for a in alphas])
     fp = (ctypes.c_void_p * n)(*[_vec(f, p.N, p.dtype, "f").value for f, p in zip(fs, plans)])
     up = (ctypes.c_void_p * n)(*[_vec(u, p.N, p.dtype, "u").value for u, p in zip(us, plans)])
-    opts = PcgOpts(float(tol), int(maxit), int(use_u0), int(precond), int(deflate),
+    opts = PcgOpts(float(tol), int(maxit), int(use_u0), _precond(precond), int(deflate),
                    int(true_residual), 0)
     infos = (PcgInfo * n)()
     st = load().pcg_solve_batched(ph, al, fp, up, n, ctypes.byref(opts), infos, _stream(stream))

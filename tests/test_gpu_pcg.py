@@ -114,3 +114,43 @@ def test_warm_start_from_solution_converges_immediately():
     u2, info2 = plan.pcg_solve(1.0, fv, u0=u, tol=1e-9)
     assert info2["iters"] <= 1
     assert rel(u2.cpu().numpy(), u.cpu().numpy()) < 1e-9
+
+
+@pytest.mark.parametrize("precond,deflate", [(0, False), (1, False), (2, False), (0, True), (1, True), (2, True)])
+def test_six_preconditioner_columns_reach_the_dense_solution(precond, deflate):
+    """none / Jacobi P_a / l2 P_b', each with and without the change of basis (the six columns
+    of the paper's iteration table)."""
+    torch, nld, f, img, F, wins, wts, plan = _problem(24, 24, 1, 5, torch_gpu().float64,
+                                                      [0.3, 0.25, 0.35, 0.3], 64, 8,
+                                                      wts=[1.0, 0.5, 2.0, 1.5])
+    alpha = 3.0
+    u, info = plan.pcg_solve(alpha, img.reshape(-1), tol=1e-11, maxit=2000, precond=precond,
+                             deflate=deflate)
+    assert info["status"] == "OK"
+    F64 = o_features(f, 1)
+    W = K.anova_dense(F64, wins, [0.3, 0.25, 0.35, 0.3], wts)
+    us = OS.dense_solve(K.system_dense(W, alpha), f.reshape(-1))
+    assert rel(u.cpu().numpy(), us) < 1e-7
+    plan.close()
+
+
+def test_l2_preconditioned_iterations_match_oracle():
+    sig, wts, alpha = [0.3, 0.25, 0.35, 0.3], [1.0, 0.5, 2.0, 1.5], 3.0
+    torch, nld, f, img, F, wins, _, plan = _problem(24, 24, 1, 6, torch_gpu().float64, sig, 64, 8,
+                                                    wts=wts)
+    F64 = o_features(f, 1)
+    fv = f.reshape(-1)
+    W = K.anova_dense(F64, wins, sig, wts)
+    eta = K.eta_from_degree(K.degree(W), wts)
+    A = K.system_dense(W, alpha)
+    pb = K.precond_l2_anova(eta, K.l2_window_degree(F64, wins, sig, wts), alpha)
+    for deflate in (True, False):
+        if deflate:
+            uo, it_o, _, _ = OS.pcg_projector(lambda v: A @ v, fv, eta, alpha, 1e-10, 500, P=pb)
+        else:
+            uo, it_o, _ = OS.pcg_jacobi(lambda v: A @ v, fv, eta, alpha, 1e-10, 500, P=pb)
+        u, info = plan.pcg_solve(alpha, img.reshape(-1), tol=1e-10, maxit=500, precond="l2",
+                                 deflate=deflate)
+        assert info["status"] == "OK"
+        assert abs(info["iters"] - it_o) <= 1, (deflate, info["iters"], it_o)
+    plan.close()
