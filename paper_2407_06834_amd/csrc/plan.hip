@@ -18,7 +18,7 @@ namespace nld {
 namespace {
 
 constexpr int kTileChunk = 2048;     // nodes per spreading / gathering workgroup
-constexpr int kCellBits = 12;        // sort key = global tile << 12 | cell within the tile
+constexpr int kMaxCellBits = 16;     // sort key = global tile << cell_bits | cell within the tile
 
 template <typename T>
 __global__ void k_features(const T* __restrict__ img, int n1, int n2, int rho, int with_pos,
@@ -82,6 +82,7 @@ struct CoordParams {
   int n[3], m;
   int ts[3], nts[3];
   unsigned tile_off;
+  int cell_bits;      // bits of the cell-within-tile part of the sort key (same for all windows)
 };
 
 __device__ inline int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
@@ -118,17 +119,17 @@ __global__ void k_coords(const T* __restrict__ F, long long N, int L,
     base[idx] = (unsigned)b[0] | ((unsigned)b[1] << 8) | ((unsigned)b[2] << 16);
     const int g = ((b[0] / p.ts[0]) * p.nts[1] + b[1] / p.ts[1]) * p.nts[2] + b[2] / p.ts[2];
     const int lc = ((b[0] % p.ts[0]) * p.ts[1] + b[1] % p.ts[1]) * p.ts[2] + b[2] % p.ts[2];
-    key[idx] = ((p.tile_off + (unsigned)g) << kCellBits) | (unsigned)lc;
+    key[idx] = ((p.tile_off + (unsigned)g) << p.cell_bits) | (unsigned)lc;
   }
 }
 
-// First position of every tile in the sorted key array (lower bound of tile << kCellBits),
+// First position of every tile in the sorted key array (lower bound of tile << cell_bits),
 // for tiles 0..ntiles.
 __global__ void k_key_offsets(const unsigned* __restrict__ keys, long long n, int ntiles,
-                              unsigned* __restrict__ off) {
+                              int cell_bits, unsigned* __restrict__ off) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k > ntiles) return;
-  const unsigned long long target = (unsigned long long)k << kCellBits;
+  const unsigned long long target = (unsigned long long)k << cell_bits;
   long long lo = 0, hi = n;
   while (lo < hi) {
     const long long mid = (lo + hi) >> 1;
@@ -652,7 +653,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     }
     if (padded * 8LL > P.lds_limit)
       throw std::invalid_argument("padded tile does not fit in LDS");
-    if ((long long)w.ts[0] * w.ts[1] * w.ts[2] > (1LL << kCellBits))
+    if ((long long)w.ts[0] * w.ts[1] * w.ts[2] > (1LL << kMaxCellBits))
       throw std::invalid_argument("tile too large for the sort key");
     max_padded = std::max<long long>(max_padded, padded);
     p.tile_off = tile_total;
@@ -664,6 +665,13 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     n_max = std::max(n_max, n);
   }
   P.n_max = n_max;
+  // bits of the cell-within-tile part of the sort key: enough for the largest tile
+  int cell_bits = 1;
+  for (int l = 0; l < L; ++l) {
+    const long long cells = (long long)P.wins[l].ts[0] * P.wins[l].ts[1] * P.wins[l].ts[2];
+    while ((1LL << cell_bits) < cells) ++cell_bits;
+  }
+  for (int l = 0; l < L; ++l) cp[l].cell_bits = cell_bits;
   std::vector<T> coef_all, coef_dv_all;   // host staging, alive until the final synchronisation
   upload_tables<T>(P, coef_all, coef_dv_all, s);
 
@@ -702,8 +710,8 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   NLD_HIP(hipGetLastError());
   int kbits = 1;
   while ((1u << kbits) < tile_total) ++kbits;
-  if (kbits + kCellBits > 32) throw std::invalid_argument("too many tiles");
-  radix_sort_pairs(key, val, LN, kbits + kCellBits, s);
+  if (kbits + cell_bits > 32) throw std::invalid_argument("too many tiles");
+  radix_sort_pairs(key, val, LN, kbits + cell_bits, s);
   P.g_idx = dalloc<int>(LN, s);
   P.g_base = dalloc<unsigned>(LN, s);
   P.g_frac = dalloc<T>(3 * LN, s);
@@ -712,7 +720,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   NLD_HIP(hipGetLastError());
   unsigned* toff = dalloc<unsigned>(tile_total + 1, s);
   hipLaunchKernelGGL(k_key_offsets, dim3((tile_total + 256) / 256), dim3(256), 0, s, key, LN,
-                     (int)tile_total, toff);
+                     (int)tile_total, cell_bits, toff);
   NLD_HIP(hipGetLastError());
   std::vector<unsigned> ht(tile_total + 1);
   NLD_HIP(hipMemcpyAsync(ht.data(), toff, (tile_total + 1) * sizeof(unsigned), hipMemcpyDeviceToHost, s));
