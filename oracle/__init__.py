@@ -12,6 +12,8 @@ Modules
   solve     dense Cholesky solve and the deflated Jacobi PCG in the paper's U basis and in
             the equivalent projector form (Sec. 4.2, 4.3, 5.3-5.4)
   csum      C/OpenMP direct sums of kernel rows (large N, sampled rows)
+  mis       mutual-information ranking of the features into windows (Sec. 5)
+  cnn       the warm-start network (not from the paper)
 
 Every function names the passage of the paper it follows.  Functions whose result has no
 independent pin are marked "parity unpinned" in their docstring.
