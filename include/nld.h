@@ -207,6 +207,21 @@ nld_status adjoint_solve(nfft_plan_t plan, double alpha, const void* f, const vo
 nld_status features_from_image(const void* img, int32_t n1, int32_t n2, int32_t rho,
                                int32_t with_pos, nld_prec prec, void* features, hipStream_t s);
 
+/* Mutual information score of every feature row against a target (paper Sec. 5: the features
+ * are ranked by this score against the noisy pixel values and the ranking is cut into windows
+ * of at most three).  The paper does not name its estimator; this is the plug-in estimate of a
+ * joint histogram.  A row x with minimum lo and maximum hi puts value v into bin
+ * min(bins - 1, floor((v - lo) * s)), s = bins / (hi - lo) (s = 0 when hi = lo), all in IEEE
+ * double; with counts n_ab of the N pairs (bin of the feature, bin of the target) and their
+ * marginals n_a, n_b,
+ *     scores[j] = sum over n_ab > 0 of (n_ab / N) log(N n_ab / (n_a n_b))   (natural log).
+ * features [d][N] and target [N]: device, element type of prec, finite values; scores [d]:
+ * device doubles written by the call.  bins: 2..64, or 0 for the largest B with
+ * B^3 <= N / 4 clamped to [4, 64].  N in [1, 2^31 - 1], d in [1, 4096].  Allocates and frees
+ * its counters stream-ordered on s; asynchronous. */
+nld_status mis_scores(const void* features, int64_t N, int32_t d, const void* target,
+                      nld_prec prec, int32_t bins, double* scores, hipStream_t s);
+
 /* Message describing the last non-OK status returned on this thread. */
 const char* nld_last_error(void);
 

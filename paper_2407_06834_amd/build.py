@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnld.so")
-SOURCES = ["api.hip", "plan.hip", "nfft.hip", "pcg.hip", "cnn.hip"]
+SOURCES = ["api.hip", "plan.hip", "nfft.hip", "pcg.hip", "cnn.hip", "mis.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

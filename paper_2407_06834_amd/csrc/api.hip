@@ -64,6 +64,19 @@ nld_status features_from_image(const void* img, int32_t n1, int32_t n2, int32_t 
   });
 }
 
+nld_status mis_scores(const void* features, int64_t N, int32_t d, const void* target,
+                      nld_prec prec, int32_t bins, double* scores, hipStream_t s) {
+  if (!features || !target || !scores) return fail(NLD_E_INVAL, "mis_scores: null pointer");
+  if (N < 1 || N > 0x7fffffffLL) return fail(NLD_E_INVAL, "mis_scores: N must be in [1, 2^31 - 1]");
+  if (d < 1 || d > 4096) return fail(NLD_E_INVAL, "mis_scores: d must be in [1, 4096]");
+  if (prec != NLD_FP32 && prec != NLD_FP64) return fail(NLD_E_INVAL, "mis_scores: bad precision");
+  if (bins != 0 && (bins < 2 || bins > 64)) return fail(NLD_E_INVAL, "mis_scores: bins must be 0 or in [2, 64]");
+  return guarded("mis_scores", [&] {
+    nld::launch_mis(features, N, d, target, prec, bins ? bins : nld::mis_default_bins(N), scores, s);
+    return NLD_OK;
+  });
+}
+
 nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t d,
                      const nld_kernel_desc* desc, hipStream_t s) {
   if (!out || !features || !desc) return fail(NLD_E_INVAL, "nfft_plan: null pointer");

@@ -258,6 +258,10 @@ void build_plan(Plan& P, const void* features, hipStream_t s);
 void release_plan(Plan& P);
 void launch_features(const void* img, int n1, int n2, int rho, int with_pos, nld_prec prec,
                      void* F, hipStream_t s);
+// feature ranking (mis.hip)
+int mis_default_bins(long long N);
+void launch_mis(const void* F, long long N, int d, const void* y, nld_prec prec, int bins,
+                double* scores, hipStream_t s);
 
 // fast summation (nfft.hip)
 enum Epilogue { EPI_ANOVA = 0, EPI_LAPLACIAN = 1, EPI_DEGREE = 2, EPI_CG_Q = 3, EPI_CG_INIT = 4,

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NOCONV", 
 # Entry points declared in include/nld.h
 SYMBOLS = ("nfft_plan", "nfft_plan_update_kernel", "nfft_plan_destroy", "nfft_plan_window_info", "nfft_plan_size",
            "degree_vector", "anova_matvec", "laplacian_matvec", "pcg_solve", "pcg_solve_batched", "adjoint_solve",
-           "features_from_image", "nld_last_error")
+           "features_from_image", "mis_scores", "nld_last_error")
 
 
 class KernelDesc(ctypes.Structure):
@@ -93,6 +93,7 @@ def load() -> ctypes.CDLL:
         "adjoint_solve": [P, D, P, P, P, P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(PcgOpts),
                           ctypes.POINTER(PcgInfo), P],
         "features_from_image": [P, I32, I32, I32, I32, I32, P, P],
+        "mis_scores": [P, I64, I32, P, I32, I32, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -317,6 +318,32 @@ def window_table(rho: int, with_pos: bool = True):
     wins = [[0, 1, centre]] if with_pos else []
     wins += [rest[s:s + 3] for s in range(0, len(rest), 3)]
     return wins
+
+
+def mis_scores(features: torch.Tensor, target: torch.Tensor, bins: int = 0, stream=None):
+    """Mutual information score (float64, on the GPU) of every feature row of the SoA matrix
+    (d, N) against the target (N); see mis_scores in nld.h."""
+    if features.dim() != 2 or not features.is_cuda:
+        raise ValueError("features: expected a 2-D CUDA tensor (d, N)")
+    if features.dtype not in (torch.float32, torch.float64):
+        raise ValueError("features: expected float32 or float64")
+    d, N = features.shape
+    features = features.contiguous()
+    y = _vec(target.reshape(-1), N, features.dtype, "target")
+    out = torch.empty(d, dtype=torch.float64, device=features.device)
+    prec = NLD_FP32 if features.dtype == torch.float32 else NLD_FP64
+    _check(load().mis_scores(ctypes.c_void_p(features.data_ptr()), N, d, y, prec, int(bins),
+                             ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def mis_window_table(features: torch.Tensor, target: torch.Tensor, bins: int = 0, size: int = 3,
+                     stream=None):
+    """Windows from the mutual-information ranking (paper Sec. 5): features in decreasing score
+    (ties by increasing index) cut into consecutive groups of `size`.  Returns (windows, scores)."""
+    sc = mis_scores(features, target, bins, stream).cpu().tolist()
+    order = sorted(range(len(sc)), key=lambda j: (-sc[j], j))
+    return [order[k:k + size] for k in range(0, len(order), size)], sc
 
 
 def pcg_solve_batched(plans, alphas, fs, us=None, tol: float = 1e-6, maxit: int = 500,

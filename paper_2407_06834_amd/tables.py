@@ -2,12 +2,14 @@
 
 Images: seeded grayscale images (rectangles and discs, intensities in [0, 1], noise std 0.1) of
 sides 64 ... 1024, standing in for the paper's scaled test images.  Features: patches without
-position (Sec. 5.2); windows from the fixed grouping (7x7 patches: 16 x 3 + 1 = 17 windows;
-11x11 patches: 40 x 3 + 1 = 41 windows); window weights 1/L as in the paper; widths sigma / 255
-for the paper's 0..255 intensities; FP64 throughout; alpha = mu / lambda.
+position (Sec. 5.2); windows from the mutual-information ranking of the features against the
+noisy pixels, as in the paper (7x7 patches: 16 x 3 + 1 = 17 windows; 11x11 patches:
+40 x 3 + 1 = 41 windows; `--windows fixed` for the fixed grouping); window weights 1/L as in
+the paper; widths sigma / 255 for the paper's 0..255 intensities; FP64 throughout;
+alpha = mu / lambda.
 
-  operator    L = 17, sigma = 50: plan set-up time (features, scaling, sort, schedules, degree
-              vector) and the time of one product W v.
+  operator    L = 17, sigma = 50: time of the features and their ranking, plan set-up time (scaling, sort,
+              schedules, degree vector) and the time of one product W v.
   solution    L = 17, sigma = 50, mu = 1e-2, lambda = 1e-1: PCG from x0 = f, tolerance 1e-7,
               at most 200 iterations; iterations, time, and the condition estimate
               2 alpha max(eta) + 1.
@@ -16,7 +18,7 @@ for the paper's 0..255 intensities; FP64 throughout; alpha = mu / lambda.
               tolerance 1e-8, at most 30 iterations ("x" when not converged).
 
     python -m paper_2407_06834_amd.tables [--sides 64,128,256,512,1024] [--only iterations]
-                                          [--all-lambdas]
+                                          [--all-lambdas] [--windows mis|fixed]
 """
 from __future__ import annotations
 
@@ -39,23 +41,39 @@ def _image(side: int, seed: int = 7):
     return torch.tensor(f, dtype=torch.float64, device="cuda")
 
 
-def _plan(img, rho: int, sigma255: float, tol: float):
+WINDOWS = "mis"
+
+
+def _windows(F, img, rho):
+    if WINDOWS == "mis":
+        return nld.mis_window_table(F, img.reshape(-1))[0]
+    return nld.window_table(rho, with_pos=False)
+
+
+def _plan(img, rho: int, sigma255: float, tol: float, times=None):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     F = nld.features_from_image(img, rho, with_pos=False)
-    wins = nld.window_table(rho, with_pos=False)
+    wins = _windows(F, img, rho)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
     L = len(wins)
-    return nld.Plan(F, wins, [sigma255 / 255.0] * L, [1.0 / L] * L, matvec_tol=tol), L
+    plan = nld.Plan(F, wins, [sigma255 / 255.0] * L, [1.0 / L] * L, matvec_tol=tol)
+    if times is not None:
+        plan.degree_vector()
+        torch.cuda.synchronize()
+        times.update(mis_ms=round((t1 - t0) * 1e3, 2),
+                     setup_ms=round((time.perf_counter() - t1) * 1e3, 2))
+    return plan, L
 
 
 def operator_table(sides):
     rows = []
+    _plan(_image(sides[0]), 3, 50.0, 1e-7, {})[0].close()     # first-use costs out of the timings
     for side in sides:
         img = _image(side)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plan, L = _plan(img, 3, 50.0, 1e-7)
-        plan.degree_vector()
-        torch.cuda.synchronize()
-        t_setup = time.perf_counter() - t0
+        times = {}
+        plan, L = _plan(img, 3, 50.0, 1e-7, times)
         v = torch.randn(side * side, dtype=torch.float64, device="cuda")
         out = torch.empty_like(v)
         plan.anova_matvec(v, out=out)
@@ -66,7 +84,7 @@ def operator_table(sides):
             plan.anova_matvec(v, out=out)
         torch.cuda.synchronize()
         t_mv = (time.perf_counter() - t0) / reps
-        rows.append(dict(side=side, n=side * side, windows=L, setup_ms=round(t_setup * 1e3, 2),
+        rows.append(dict(side=side, n=side * side, windows=L, **times,
                          product_ms=round(t_mv * 1e3, 3)))
         plan.close()
     return rows
@@ -121,14 +139,17 @@ def main():
     ap.add_argument("--sides", default="64,128,256,512,1024")
     ap.add_argument("--only", default="")
     ap.add_argument("--all-lambdas", action="store_true")
+    ap.add_argument("--windows", choices=("mis", "fixed"), default="mis")
     args = ap.parse_args()
+    global WINDOWS
+    WINDOWS = args.windows
     sides = [int(x) for x in args.sides.split(",")]
     nld.load()
     todo = args.only.split(",") if args.only else ["operator", "solution", "iterations"]
     if "operator" in todo:
         r = operator_table(sides)
         print(json.dumps({"operator": r}), flush=True)
-        print(markdown(r, ["side", "n", "windows", "setup_ms", "product_ms"]), flush=True)
+        print(markdown(r, ["side", "n", "windows", "mis_ms", "setup_ms", "product_ms"]), flush=True)
     if "solution" in todo:
         r = solution_table(sides)
         print(json.dumps({"solution": r}), flush=True)

@@ -89,6 +89,12 @@ def test_invalid_arguments_rejected_on_host(lib):
     grad = (ctypes.c_double * 3)()
     assert L.adjoint_solve(None, 1.0, fake, fake, fake, fake, grad, ctypes.byref(opts),
                            ctypes.byref(info), None) == nld.NLD_E_INVAL
+    assert L.mis_scores(None, 10, 2, fake, 0, 0, fake, None) == nld.NLD_E_INVAL and "null" in err()
+    assert L.mis_scores(fake, 0, 2, fake, 0, 0, fake, None) == nld.NLD_E_INVAL
+    assert L.mis_scores(fake, 10, 0, fake, 0, 0, fake, None) == nld.NLD_E_INVAL
+    assert L.mis_scores(fake, 10, 2, fake, 0, 1, fake, None) == nld.NLD_E_INVAL and "bins" in err()
+    assert L.mis_scores(fake, 10, 2, fake, 0, 65, fake, None) == nld.NLD_E_INVAL
+    assert L.mis_scores(fake, 10, 2, fake, 3, 8, fake, None) == nld.NLD_E_INVAL
     from paper_2407_06834_amd import cnn
     C = cnn._lib()
     assert C.cnn_create(None, 2, 0) == nld.NLD_E_INVAL
