@@ -206,6 +206,7 @@ struct Plan {
   double* sumv = nullptr;          // sum of the vector (windows without kept dimensions)
   bool has_flat = false;           // some window has no kept dimension: K_l = 1 1^T
   bool have_D = false;
+  bool have_dl = false;            // dl / dls hold the per-window degrees of the current widths
   // l2 preconditioner (Sec. 4.3.1): multiplier tables of the kernels exp(-r^2 / (sigma_l^2 / 2))
   // on the same grids, window descriptors with weights w_l^2, and D2 (built on first use)
   void* coef_b = nullptr;

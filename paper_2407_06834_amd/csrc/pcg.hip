@@ -359,10 +359,11 @@ nld_status run_adjoint(Plan& P, double alpha, const void* u, const void* g, void
   alloc(&P.yks, LN * P.elem);
   alloc(&P.grid_save, (size_t)P.grid_total * P.elem);
   alloc((void**)&P.adj_part, (size_t)257 * (4 * P.L + 3) * sizeof(double));
-  if (!P.dl) {
-    alloc(&P.dl, LN * P.elem);
-    alloc(&P.dls, LN * P.elem);
+  alloc(&P.dl, LN * P.elem);
+  alloc(&P.dls, LN * P.elem);
+  if (!P.have_dl) {
     matvec_parts(P, P.ones, P.dl, P.dls, s);     // per-window degrees K_l 1 and K^s_l 1
+    P.have_dl = true;
   }
   matvec_parts(P, u, P.yk, P.yks, s);
   std::vector<double> sums;

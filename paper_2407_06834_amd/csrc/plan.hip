@@ -1051,6 +1051,7 @@ static void update_kernel_t(Plan& P, const double* sigma, const double* weight, 
   NLD_HIP(hipStreamSynchronize(s));
   P.have_D = false;
   P.have_D2 = false;
+  P.have_dl = false;
 }
 
 // Multiplier tables of exp(-r^2 / (sigma_l^2 / 2)) on the plan's grids (the squared kernels:

@@ -109,3 +109,33 @@ def test_autograd_function_fp32():
                                  wins, dict(bandwidth=64, cutoff=8), 1e-11)
     torch.sum((u64 - ucv.double()) ** 2).backward()
     assert abs(float(la.grad) - float(la2.grad)) < 1e-3 * abs(float(la2.grad))
+
+
+def test_adjoint_after_kernel_update_matches_fresh_plan():
+    # the per-window degrees the gradient uses must follow nfft_plan_update_kernel
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    uc, f = make_image(230, 40, 40, 4, 3, 0.15)
+    img = torch.tensor(f, dtype=torch.float64, device="cuda")
+    F = nld.features_from_image(img, 1)
+    wins = nld.window_table(1)
+    fv = img.reshape(-1)
+    ucv = torch.tensor(uc.reshape(-1), device="cuda")
+    sig0, sig1, wts = [0.2, 0.25, 0.2, 0.3], [0.22, 0.3, 0.21, 0.3], [1.0, 0.7, 1.3, 0.5]
+
+    def grad_of(plan):
+        u, _ = plan.pcg_solve(0.8, fv, tol=1e-12)
+        _, g, info = plan.adjoint_solve(0.8, fv, u, 2.0 * (u - ucv), tol=1e-12)
+        assert info["status"] == "OK"
+        return g
+
+    plan = nld.Plan(F, wins, sig0, wts, bandwidth=64, cutoff=8)
+    grad_of(plan)
+    assert plan.update_kernel(sig1, wts)
+    g_upd = grad_of(plan)
+    plan.close()
+    fresh = nld.Plan(F, wins, sig1, wts, bandwidth=64, cutoff=8)
+    g_new = grad_of(fresh)
+    fresh.close()
+    # the two plans scale the nodes differently, so they agree to the summation accuracy
+    assert np.abs(g_upd - g_new).max() < 1e-5 * np.abs(g_new).max()
