@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <type_traits>
+#include <utility>
 #include <stdexcept>
 
 #include "nld_device.h"
@@ -39,6 +40,39 @@ __device__ __forceinline__ int tile_origin(const WinDev& w, int tile, int dd) {
   else if (dd == 1) tt = (tile / w.nts[2]) % w.nts[1];
   else tt = tile / (w.nts[2] * w.nts[1]);
   return tt * w.ts[dd];
+}
+
+// f(std::integral_constant<int, 0>{}), ..., f(std::integral_constant<int, N - 1>{})
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
+// Slot layout.  Along each dimension a padded tile of pe = ts + 2m - 1 cells splits into the
+// m - 1 cells that fold into the left neighbour tile, the ts cells of the tile itself and the
+// m cells that fold into the right neighbour (an unused dimension: one cell, one part).  A slot
+// stores the 27 blocks these parts form one after the other (lexicographic order of the parts,
+// cells row-major inside a block), so that the fold reads each block it needs as one
+// contiguous range instead of short pieces of many padded rows.
+struct SlotPart {
+  int pre, sz;   // first padded index and extent of the part that holds padded index x
+};
+__device__ __forceinline__ SlotPart slot_part(int x, int a, int b, int pe) {
+  return x < a ? SlotPart{0, a} : (x < a + b ? SlotPart{a, b} : SlotPart{a + b, pe - a - b});
+}
+__device__ __forceinline__ int slot_index(const WinDev& w, int x0, int x1, int x2) {
+  const int a0 = w.taps[0] > 1 ? w.m - 1 : 0, a1 = w.taps[1] > 1 ? w.m - 1 : 0,
+            a2 = w.taps[2] > 1 ? w.m - 1 : 0;
+  const SlotPart q0 = slot_part(x0, a0, w.ts[0], w.pe[0]);
+  const SlotPart q1 = slot_part(x1, a1, w.ts[1], w.pe[1]);
+  const SlotPart q2 = slot_part(x2, a2, w.ts[2], w.pe[2]);
+  const int pe1 = w.pe[1], pe2 = w.pe[2];
+  return q0.pre * pe1 * pe2 + q0.sz * (q1.pre * pe2 + q1.sz * q2.pre) +
+         ((x0 - q0.pre) * q1.sz + (x1 - q1.pre)) * q2.sz + (x2 - q2.pre);
 }
 
 
@@ -102,9 +136,10 @@ __device__ __forceinline__ void poly_row(P psi, T fr, T* wt) {
 // 2^(29 - e) plus a 32-bit remainder word 2^20 finer, FP64 data: one 64-bit word scaled by
 // 2^(61 - e)): integer addition is exact and associative, so the result does not depend on the
 // order in which the wavefronts add (reproducible), and ds_add_u32 / ds_add_u64 are fast where
-// LDS float atomics are not.
-// The slot is then written back in the working precision; the fold kernel sums the slots that
-// cover each grid cell.
+// LDS float atomics are not.  (Packing the two FP32 words into one 64-bit add measured slower:
+// the lanes' 8-byte addresses meet in fewer LDS banks.)
+// The slot is then written back in the working precision, in the slot layout above; the fold
+// kernel sums the slots that cover each grid cell.
 template <typename T, int W, int TD>
 __global__ void __launch_bounds__(kSpreadThreads)
 k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int job0,
@@ -281,11 +316,24 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   }
   if (cur != kNone) flush();
   __syncthreads();
-  const double inv = 1.0 / scale;
-  for (int c = threadIdx.x; c < cells; c += kSpreadThreads) {
-    double val = (double)(SAcc)acc[c];
-    if constexpr (kTwo) val += (double)(SAcc)acc_lo[c] * (1.0 / (double)kLoScale);
-    out[c] = (T)(val * inv);
+  // the two FP32 words combine exactly in double (at most 50 significant bits)
+  const double inv = kTwo ? 1.0 / (scale * (double)kLoScale) : 1.0 / scale;
+  // a thread owns columns (x1, x2) of the padded tile and walks them along the first dimension
+  const int pe0 = w.pe[0], a0 = w.taps[0] > 1 ? w.m - 1 : 0;
+  const int a1 = w.taps[1] > 1 ? w.m - 1 : 0, a2 = w.taps[2] > 1 ? w.m - 1 : 0;
+  for (int col = threadIdx.x; col < s01; col += kSpreadThreads) {
+    const int x1 = col / pe2, x2 = col - x1 * pe2;
+    const SlotPart q1 = slot_part(x1, a1, w.ts[1], pe1), q2 = slot_part(x2, a2, w.ts[2], pe2);
+    const int in_block = (x1 - q1.pre) * q2.sz + (x2 - q2.pre);
+    for (int x0 = 0; x0 < pe0; ++x0) {
+      const SlotPart q0 = slot_part(x0, a0, w.ts[0], pe0);
+      const int o = q0.pre * s01 + q0.sz * (q1.pre * pe2 + q1.sz * q2.pre) +
+                    (x0 - q0.pre) * q1.sz * q2.sz + in_block;
+      const int c = x0 * s01 + col;
+      double val = (double)(SAcc)acc[c];
+      if constexpr (kTwo) val = val * (double)kLoScale + (double)(SAcc)acc_lo[c];
+      out[o] = (T)(val * inv);
+    }
   }
 }
 
@@ -337,7 +385,6 @@ k_fold(const WinDev* __restrict__ wins, const FoldJob* __restrict__ jobs,
       cn[k] = q;
     }
   }
-  const int pe1 = w.pe[1], pe2 = w.pe[2];
   T sum = (T)0;
   for (int a = 0; a < cn[0]; ++a)
     for (int bq = 0; bq < cn[1]; ++bq)
@@ -345,7 +392,7 @@ k_fold(const WinDev* __restrict__ wins, const FoldJob* __restrict__ jobs,
         const int gt = w.tile_off + (((ct[0][a] << w.lnts[1]) + ct[1][bq]) << w.lnts[2]) + ct[2][e];
         const int ns = tile_nslot[gt];
         if (ns == 0) continue;
-        const long long pidx = ((long long)cl[0][a] * pe1 + cl[1][bq]) * pe2 + cl[2][e];
+        const int pidx = slot_index(w, cl[0][a], cl[1][bq], cl[2][e]);
         const auto src = padded + (long long)tile_slot0[gt] * slot_stride + pidx;
         for (int k = 0; k < ns; ++k) sum += src[(long long)k * slot_stride];
       }
@@ -373,7 +420,6 @@ k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int 
   const int tc1 = (job.tile >> w.lnts[2]) & (w.nts[1] - 1);
   const int tc0 = job.tile >> (w.lnts[2] + w.lnts[1]);
   const int left = w.m - 1, pe = w.pe[0];
-  const long long pe2 = pe, pe12 = (long long)pe * pe;
   T acc[TS];
 #pragma unroll
   for (int k = 0; k < TS; ++k) acc[k] = (T)0;
@@ -395,11 +441,11 @@ k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int 
         if (ns == 0) continue;
         const int p1 = x1 - s1, p2 = x2 - s2;        // padded indices of this column
         if (p1 < 0 || p1 >= pe || p2 < 0 || p2 >= pe) continue;
-        const auto src = padded + (long long)tile_slot0[gt] * slot_stride + p1 * pe2 + p2;
+        const auto src = padded + (long long)tile_slot0[gt] * slot_stride;
 #pragma unroll
         for (int x0 = 0; x0 < TS; ++x0) {
           if (x0 < lo0 || x0 >= hi0) continue;
-          const auto q = src + (long long)(x0 - s0) * pe12;
+          const auto q = src + slot_index(w, x0 - s0, p1, p2);
           T sum = (T)0;
           for (int k = 0; k < ns; ++k) sum += q[(long long)k * slot_stride];
           acc[x0] += sum;
@@ -414,15 +460,19 @@ k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int 
     g[((long long)(o0 + x0) * w.n[1] + (o1 + x1)) * w.n[2] + (o2 + x2)] = acc[x0];
 }
 
-// Fold of a 3-D window with 8^3 tiles and cutoff M known at compile time: the same neighbour
-// and slot order as k_fold3 (so the same sums bit for bit), with every neighbour's overlap along
-// the first dimension fixed at compile time and the slot tables read up front, so that the
-// loads of all neighbours can be in flight together.
+// Fold of a 3-D window with 8^3 tiles and cutoff M known at compile time, one wavefront per
+// tile.  Each of the 27 neighbours contributes one block of its slot (the slot layout stores it
+// contiguously): the wavefront reads the block with consecutive lanes on consecutive cells and
+// adds it into the tile held in LDS, neighbour after neighbour and slot after slot, the order of
+// k_fold3 (so the same sums bit for bit).  Block shapes and positions are compile-time
+// constants; the lanes of one block hit distinct cells, and one wavefront keeps the LDS
+// updates in order.
 template <typename T, int M>
 __global__ void __launch_bounds__(64)
 k_fold3m(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int job0,
          const ImgDev* __restrict__ imgs, int check) {
   constexpr int TS = 8, LEFT = M - 1, PE = TS + 2 * M - 1;
+  __shared__ T tile[TS * TS * TS];
   const Fold3Job job = jobs[job0 + blockIdx.x];
   const WinDev& w = wins[job.win];
   if (check && imgs[w.img].st->done) return;
@@ -430,7 +480,7 @@ k_fold3m(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int
   const long long slot_stride = w.slot_stride;
   ConstPtr<int> tile_slot0 = (ConstPtr<int>)w.tile_slot0;
   ConstPtr<int> tile_nslot = (ConstPtr<int>)w.tile_nslot;
-  const int x2 = threadIdx.x % TS, x1 = threadIdx.x / TS;
+  const int lane = threadIdx.x;
   const int tc2 = job.tile & (w.nts[2] - 1);
   const int tc1 = (job.tile >> w.lnts[2]) & (w.nts[1] - 1);
   const int tc0 = job.tile >> (w.lnts[2] + w.lnts[1]);
@@ -445,59 +495,60 @@ k_fold3m(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int
     ns[n] = tile_nslot[gt];
     s0t[n] = tile_slot0[gt];
   }
-  T acc[TS];
 #pragma unroll
-  for (int k = 0; k < TS; ++k) acc[k] = (T)0;
+  for (int k = 0; k < TS * TS * TS / 64; ++k) tile[lane + 64 * k] = (T)0;
   bool multi = false;
 #pragma unroll
   for (int n = 0; n < 27; ++n) multi = multi || ns[n] > 1;
-  if (!multi) {
-    // at most one slot per neighbour: empty neighbours skipped (uniform branch), the others read
-    // without lane-dependent branches (address clamped into the neighbour's slot, value masked)
+  // Neighbour offset d along a dimension selects the block of its slot that folds into this
+  // tile: d = -1 its right part (M cells, padded start LEFT + TS) onto cells [0, M), d = 0 the
+  // tile part (TS cells, start LEFT) onto [0, TS), d = +1 its left part (M - 1 cells, start 0)
+  // onto [TS - LEFT, TS).
+  constexpr auto pre = [](int d) { return d < 0 ? LEFT + TS : (d == 0 ? LEFT : 0); };
+  constexpr auto sz = [](int d) { return d < 0 ? M : (d == 0 ? TS : LEFT); };
+  constexpr auto off = [](int d) { return d > 0 ? TS - LEFT : 0; };
+  // one neighbour's block: load (one slot, or the sum of its slots in order), then add
+  auto fold_block = [&](auto n_c, auto multi_c) {
+    constexpr int n = decltype(n_c)::value;
+    constexpr bool MULTI = decltype(multi_c)::value;
+    constexpr int d0 = n / 9 - 1, d1 = (n / 3) % 3 - 1, d2 = n % 3 - 1;
+    constexpr int sz0 = sz(d0), sz1 = sz(d1), sz2 = sz(d2), bs = sz0 * sz1 * sz2;
+    constexpr int nit = (bs + 63) / 64;
+    if constexpr (bs > 0) {
+      if (ns[n] == 0) return;                                 // uniform: empty neighbour tile
+      constexpr int base = pre(d0) * PE * PE + sz0 * (pre(d1) * PE + sz1 * pre(d2));
+      const long long src = (long long)s0t[n] * slot_stride + base;
+      T val[nit];
 #pragma unroll
-    for (int n = 0; n < 27; ++n) {
-      const int d0 = n / 9 - 1, d1 = (n / 3) % 3 - 1, d2 = n % 3 - 1;
-      const int s0 = d0 * TS - LEFT, s1 = d1 * TS - LEFT, s2 = d2 * TS - LEFT;
-      const int lo0 = s0 > 0 ? s0 : 0, hi0 = (s0 + PE < TS) ? s0 + PE : TS;
-      if (lo0 >= hi0) continue;                               // compile-time
-      if ((s1 > 0 ? s1 : 0) >= ((s1 + PE < TS) ? s1 + PE : TS)) continue;
-      if ((s2 > 0 ? s2 : 0) >= ((s2 + PE < TS) ? s2 + PE : TS)) continue;
-      if (ns[n] == 0) continue;                               // uniform: empty neighbour tile
-      const int p1 = x1 - s1, p2 = x2 - s2;
-      const bool ok = p1 >= 0 && p1 < PE && p2 >= 0 && p2 < PE;
-      const long long base = (long long)s0t[n] * slot_stride + (ok ? p1 * PE + p2 : 0);
+      for (int it = 0; it < nit; ++it) {
+        const int e = lane + 64 * it;
+        const int ec = e < bs ? e : 0;                        // lanes past the block reread cell 0
+        if constexpr (!MULTI) {
+          val[it] = padded[src + ec];
+        } else {
+          T sum = (T)0;
+          for (int k = 0; k < ns[n]; ++k) sum += padded[src + (long long)k * slot_stride + ec];
+          val[it] = sum;
+        }
+      }
 #pragma unroll
-      for (int x0 = 0; x0 < TS; ++x0) {
-        if (x0 < lo0 || x0 >= hi0) continue;                  // compile-time
-        const T val = padded[base + (long long)(x0 - s0) * PE * PE];
-        acc[x0] += ok ? val : (T)0;
+      for (int it = 0; it < nit; ++it) {
+        const int e = lane + 64 * it;
+        if (e >= bs) continue;
+        const int r2 = e % sz2, r1 = (e / sz2) % sz1, r0 = e / (sz1 * sz2);
+        tile[((r0 + off(d0)) * TS + (r1 + off(d1))) * TS + (r2 + off(d2))] += val[it];
       }
     }
-  } else {
-    for (int n = 0; n < 27; ++n) {
-      const int d0 = n / 9 - 1, d1 = (n / 3) % 3 - 1, d2 = n % 3 - 1;
-      const int s0 = d0 * TS - LEFT, s1 = d1 * TS - LEFT, s2 = d2 * TS - LEFT;
-      const int lo0 = s0 > 0 ? s0 : 0, hi0 = (s0 + PE < TS) ? s0 + PE : TS;
-      if (lo0 >= hi0) continue;
-      if ((s1 > 0 ? s1 : 0) >= ((s1 + PE < TS) ? s1 + PE : TS)) continue;
-      if ((s2 > 0 ? s2 : 0) >= ((s2 + PE < TS) ? s2 + PE : TS)) continue;
-      if (ns[n] == 0) continue;
-      const int p1 = x1 - s1, p2 = x2 - s2;
-      if (p1 < 0 || p1 >= PE || p2 < 0 || p2 >= PE) continue;
-      const auto src = padded + (long long)s0t[n] * slot_stride + p1 * PE + p2;
-      for (int x0 = lo0; x0 < hi0; ++x0) {
-        const auto q = src + (long long)(x0 - s0) * PE * PE;
-        T sum = (T)0;
-        for (int k = 0; k < ns[n]; ++k) sum += q[(long long)k * slot_stride];
-        acc[x0] += sum;
-      }
-    }
-  }
+  };
+  if (!multi) static_for<27>([&](auto n_c) { fold_block(n_c, std::false_type{}); });
+  else static_for<27>([&](auto n_c) { fold_block(n_c, std::true_type{}); });
+  __syncthreads();
   T __attribute__((address_space(1)))* g = (T __attribute__((address_space(1)))*)w.grid + w.grid_off;
   const int o0 = tc0 * TS, o1 = tc1 * TS, o2 = tc2 * TS;
+  const int x2 = lane % TS, x1 = lane / TS;
 #pragma unroll
   for (int x0 = 0; x0 < TS; ++x0)
-    g[((long long)(o0 + x0) * w.n[1] + (o1 + x1)) * w.n[2] + (o2 + x2)] = acc[x0];
+    g[((long long)(o0 + x0) * w.n[1] + (o1 + x1)) * w.n[2] + (o2 + x2)] = tile[(x0 * TS + x1) * TS + x2];
 }
 
 // ---------------------------------------------------------------------------- convolution
