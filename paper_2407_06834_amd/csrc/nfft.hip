@@ -950,11 +950,14 @@ k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     const int s0 = (TD == 3) ? o0 - m + 1 : o0;
     const int s1 = (TD >= 2) ? o1 - m + 1 : o1;
     const int s2 = o2 - m + 1;
-    const int cells = pe0 * pe1 * pe2;
-    for (int c = threadIdx.x; c < cells; c += kGatherThreads) {
-      const int a2 = c % pe2, a1 = (c / pe2) % pe1, a0 = c / (pe2 * pe1);
-      const int g0 = wrap(s0 + a0, n0), g1 = wrap(s1 + a1, n1), g2 = wrap(s2 + a2, n2);
-      tile[c] = h[((long long)g0 * n1 + g1) * n2 + g2];
+    // grid sizes are powers of two: periodic wrap by masking; a thread owns columns (a1, a2)
+    // of the padded tile and walks them along the first dimension
+    const int s01 = pe1 * pe2;
+    for (int col = threadIdx.x; col < s01; col += kGatherThreads) {
+      const int a1 = col / pe2, a2 = col - a1 * pe2;
+      const long long row = (long long)((s1 + a1) & (n1 - 1)) * n2 + ((s2 + a2) & (n2 - 1));
+      for (int a0 = 0; a0 < pe0; ++a0)
+        tile[a0 * s01 + col] = h[(long long)((s0 + a0) & (n0 - 1)) * n1 * n2 + row];
     }
     __syncthreads();
     if constexpr (PSI_LDS) gather_nodes<T, W, TD, true>(job, w, tile, h, (LdsPtr<T>)s_psi, o0, o1, o2);
