@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes of one FP32 Laplacian product on this workload, from the rocprofv3 counter runs kept
 # in profiles/nfft_laplacian_512_fp32_hbm_traffic.md, valid for the kernel sources of that hash
-TRAFFIC = {"sha1": "a1addf1e69dcfe7980b8df702ec92b527881204f", "bytes": 1351510014}
+TRAFFIC = {"sha1": "bb615af610d432afdec6f02d38cd04402fdd7ef8", "bytes": 1106430304}
 KERNEL_SOURCES = ("paper_2407_06834_amd/csrc/nfft.hip", "paper_2407_06834_amd/csrc/plan.hip",
                   "paper_2407_06834_amd/csrc/nld_internal.h", "paper_2407_06834_amd/csrc/nld_device.h")
 
