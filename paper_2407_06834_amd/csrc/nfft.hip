@@ -617,12 +617,32 @@ __device__ __forceinline__ void dft_reg(Cx<T>* v) {
   }
 }
 
+// Exchange-buffer layout of the four-step transform.  Line ql holds element (k2, k) (k2 < A,
+// k < B) at ql * XS + k2 * B + (k XOR ((k2 / R) mod B)) when B >= 8: the XOR spreads the lanes
+// that hold consecutive k2 over different banks, and XS = N + 8 (an odd multiple of 8 complex
+// values) puts neighbouring lines in opposite halves of the banks, so that both exchange
+// patterns (lane j1 writing column j1, lane j1 reading rows j1 R .. j1 R + R - 1) hit every bank
+// equally often.  (With XS = N + 1 and no XOR the rows pattern put all eight lanes of a line in
+// one bank.)  Narrow lines (B = 4) keep the plain layout, which measured no worse there.
+template <int B, int R, bool SWZ>
+__device__ __forceinline__ int xpos(int k2, int k) {
+  return k2 * B + (SWZ ? (k ^ ((k2 / R) & (B - 1))) : k);
+}
+
 template <int N> struct FftShape {
   static constexpr int A = (N >= 128) ? 16 : 8;   // values per thread
   static constexpr int B = N / A;                 // threads per complex line
+  static constexpr int R = A / B > 0 ? A / B : 1; // length-B DFTs per thread
   static constexpr int CL = (256 / B < N / 2) ? 256 / B : N / 2;   // complex lines per workgroup
   static constexpr int RL = 2 * CL;               // real lines per workgroup
-  static constexpr int SP = N + 1;                // padded LDS line stride (elements)
+  static constexpr int SP = N + 1;                // padded LDS line stride of the real lines
+  static constexpr bool SWZ = B >= 8;
+  static constexpr int XS = SWZ ? N + 8 : N + 1;  // exchange line stride (complex values)
+  template <typename T>
+  static constexpr size_t main_bytes() {          // real lines and exchange buffer share bytes
+    const size_t a = (size_t)RL * SP * sizeof(T), b = (size_t)CL * XS * 2 * sizeof(T);
+    return a > b ? a : b;
+  }
 };
 
 template <typename T, int N>
@@ -634,11 +654,11 @@ k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int jo
   if (check && imgs[w.img].st->done) return;
   T __attribute__((address_space(1)))* grid = (T __attribute__((address_space(1)))*)w.grid;
   using S = FftShape<N>;
-  constexpr int A = S::A, B = S::B, CL = S::CL, RL = S::RL, SP = S::SP;
+  constexpr int A = S::A, B = S::B, CL = S::CL, RL = S::RL, SP = S::SP, XS = S::XS;
   extern __shared__ unsigned char smem_raw[];
   T* stage = reinterpret_cast<T*>(smem_raw);                      // RL * SP reals
-  Cx<T>* ex = reinterpret_cast<Cx<T>*>(smem_raw);                 // CL * SP complex (same bytes)
-  Cx<T>* tw = reinterpret_cast<Cx<T>*>(smem_raw + (size_t)RL * SP * sizeof(T));  // N twiddles
+  Cx<T>* ex = reinterpret_cast<Cx<T>*>(smem_raw);                 // CL * XS complex (same bytes)
+  Cx<T>* tw = reinterpret_cast<Cx<T>*>(smem_raw + S::template main_bytes<T>());  // N twiddles
   for (int q = threadIdx.x; q < N; q += 256) {
     T sn, cs;
     if constexpr (sizeof(T) == 4) sincospif(-2.0f * (float)q / (float)N, &sn, &cs);
@@ -675,17 +695,17 @@ k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int jo
   __syncthreads();
   if (act) {
 #pragma unroll
-    for (int k2 = 0; k2 < A; ++k2) ex[ql * SP + k2 * B + j1] = v[k2];
+    for (int k2 = 0; k2 < A; ++k2) ex[ql * XS + xpos<B, S::R, S::SWZ>(k2, j1)] = v[k2];
   }
   __syncthreads();
-  constexpr int R = A / B > 0 ? A / B : 1;       // length-B DFTs per thread
+  constexpr int R = S::R;
   if (act) {
     Cx<T> u[R][B];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int k2 = j1 * R + r;
 #pragma unroll
-      for (int k1 = 0; k1 < B; ++k1) u[r][k1] = ex[ql * SP + k2 * B + k1];
+      for (int k1 = 0; k1 < B; ++k1) u[r][k1] = ex[ql * XS + xpos<B, R, S::SWZ>(k2, k1)];
       dft_reg<T, B, false>(u[r]);                 // u[r][k1] = X[k2 + A k1]
 #pragma unroll
       for (int k1 = 0; k1 < B; ++k1) {
@@ -697,13 +717,13 @@ k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int jo
 #pragma unroll
       for (int j = 0; j < B; ++j) u[r][j] = cmulc(u[r][j], tw[(j * k2) & (N - 1)]);
 #pragma unroll
-      for (int j = 0; j < B; ++j) ex[ql * SP + k2 * B + j] = u[r][j];
+      for (int j = 0; j < B; ++j) ex[ql * XS + xpos<B, R, S::SWZ>(k2, j)] = u[r][j];
     }
   }
   __syncthreads();
   if (act) {
 #pragma unroll
-    for (int k2 = 0; k2 < A; ++k2) v[k2] = ex[ql * SP + k2 * B + j1];
+    for (int k2 = 0; k2 < A; ++k2) v[k2] = ex[ql * XS + xpos<B, R, S::SWZ>(k2, j1)];
     dft_reg<T, A, true>(v);                       // v[j2] = x'[j1 + B j2]
   }
   __syncthreads();
@@ -735,10 +755,14 @@ k_conv(const WinDev* __restrict__ wins, const ConvJob* __restrict__ jobs, int jo
 template <int N> struct PlaneShape {
   static constexpr int A = (N >= 128) ? 16 : 8;
   static constexpr int B = N / A;
+  static constexpr int R = A / B > 0 ? A / B : 1;
   static constexpr int CL = N / 2;                // complex lines: every line of the plane
   static constexpr int THREADS = 512;
-  static constexpr int PS = N + 1;                // plane row stride (floats)
-  static constexpr int XS = N + 1;                // exchange line stride (complex), aliasing the plane
+  // plane row stride (floats): N + 5 spreads both the row and the column accesses of a
+  // wavefront over the banks better than N + 1 (which put every other lane pair in one bank)
+  static constexpr int PS = N + 5;
+  static constexpr bool SWZ = B >= 8;
+  static constexpr int XS = SWZ ? N + 8 : N + 1;  // exchange line stride (complex), aliasing the plane
   static constexpr size_t lds() {
     const size_t plane = (size_t)N * PS * sizeof(float), exch = (size_t)CL * XS * 2 * sizeof(float);
     return (plane > exch ? plane : exch) + (size_t)N * 2 * sizeof(float);
@@ -797,17 +821,17 @@ k_plane(const WinDev* __restrict__ wins, const PlaneJob* __restrict__ jobs, int 
     __syncthreads();   // every line is in registers: the plane's bytes become the exchange buffer
     if (act) {
 #pragma unroll
-      for (int k2 = 0; k2 < A; ++k2) ex[ql * XS + k2 * B + j1] = v[k2];
+      for (int k2 = 0; k2 < A; ++k2) ex[ql * XS + xpos<B, S::R, S::SWZ>(k2, j1)] = v[k2];
     }
     __syncthreads();
-    constexpr int R = A / B > 0 ? A / B : 1;
+    constexpr int R = S::R;
     if (act) {
       Cx<T> u[R][B];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int k2 = j1 * R + r;
 #pragma unroll
-        for (int k1 = 0; k1 < B; ++k1) u[r][k1] = ex[ql * XS + k2 * B + k1];
+        for (int k1 = 0; k1 < B; ++k1) u[r][k1] = ex[ql * XS + xpos<B, R, S::SWZ>(k2, k1)];
         dft_reg<T, B, false>(u[r]);
 #pragma unroll
         for (int k1 = 0; k1 < B; ++k1) {
@@ -819,13 +843,13 @@ k_plane(const WinDev* __restrict__ wins, const PlaneJob* __restrict__ jobs, int 
 #pragma unroll
         for (int j = 0; j < B; ++j) u[r][j] = cmulc(u[r][j], tw[(j * k2) & (N - 1)]);
 #pragma unroll
-        for (int j = 0; j < B; ++j) ex[ql * XS + k2 * B + j] = u[r][j];
+        for (int j = 0; j < B; ++j) ex[ql * XS + xpos<B, R, S::SWZ>(k2, j)] = u[r][j];
       }
     }
     __syncthreads();
     if (act) {
 #pragma unroll
-      for (int k2 = 0; k2 < A; ++k2) v[k2] = ex[ql * XS + k2 * B + j1];
+      for (int k2 = 0; k2 < A; ++k2) v[k2] = ex[ql * XS + xpos<B, R, S::SWZ>(k2, j1)];
       dft_reg<T, A, true>(v);
     }
     __syncthreads();   // the exchange buffer is read: its bytes hold the plane again
@@ -1142,7 +1166,7 @@ void tiles_dispatch(const LaunchSet& ls, VecArg in, int check, hipStream_t s, bo
 template <typename T, int N>
 void launch_conv(const LaunchSet& ls, int ax, int j0, int nj, int check, hipStream_t s) {
   using S = FftShape<N>;
-  const size_t lds = (size_t)S::RL * S::SP * sizeof(T) + (size_t)N * 2 * sizeof(T);
+  const size_t lds = S::template main_bytes<T>() + (size_t)N * 2 * sizeof(T);
   allow_lds(k_conv<T, N>, lds);
   hipLaunchKernelGGL((k_conv<T, N>), dim3(nj), dim3(256), lds, s, ls.d_wins, ls.d_conv[ax], j0, ax,
                      ls.d_imgs, check);
@@ -1342,6 +1366,10 @@ void matvec_set_t(const LaunchSet& ls, VecArg in, VecArg out, double* Dout, Epil
 }
 
 }  // namespace
+
+size_t plane_lds_bytes(int n) {
+  return n == 64 ? PlaneShape<64>::lds() : n == 128 ? PlaneShape<128>::lds() : (size_t)1 << 40;
+}
 
 void matvec_parts(Plan& P, const void* v, void* yk, void* yks, hipStream_t s) {
   if (P.prec == NLD_FP32) matvec_parts_t<float>(P, v, yk, yks, s);

@@ -265,6 +265,7 @@ void launch_mis(const void* F, long long N, int d, const void* y, nld_prec prec,
                 double* scores, hipStream_t s);
 
 // fast summation (nfft.hip)
+size_t plane_lds_bytes(int n);   // LDS of the fused plane convolution for n = 64 or 128
 enum Epilogue { EPI_ANOVA = 0, EPI_LAPLACIAN = 1, EPI_DEGREE = 2, EPI_CG_Q = 3, EPI_CG_INIT = 4,
                 EPI_CG_TRUE = 5 };
 // Runs the per-window fast summations on the input of every image of the set and the window

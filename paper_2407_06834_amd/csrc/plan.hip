@@ -808,10 +808,8 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   for (int l = 0; l < L; ++l) {
     const WinDev& w = P.wins[l];
     const int n = w.n[0];
-    const long long need = std::max((long long)n * (n + 1) * 4, (long long)(n / 2) * (n + 1) * 8) +
-                           (long long)n * 8;
     fused[l] = !no_plane && P.prec == NLD_FP32 && w.t == 3 && n == w.n[1] && n == w.n[2] &&
-               (n == 64 || n == 128) && need <= P.lds_limit;
+               (n == 64 || n == 128) && (long long)plane_lds_bytes(n) <= P.lds_limit;
   }
   std::vector<PlaneJob> pj;
   for (int gi = 0; gi < 2; ++gi) {
