@@ -1040,12 +1040,34 @@ k_reduce(const WinDev* __restrict__ wins, const ImgDev* __restrict__ imgs, Reduc
   const double alpha = cg ? st->alpha : 0.0;
   const double mean_f = cg ? st->mean_f : 0.0;
   const T* f = cg ? reinterpret_cast<const T*>(im.vec[V_F]) : nullptr;
+  // the image's window weights and per-window results, read once per block (the output
+  // stores below could alias the descriptors, so the compiler would reload them per element);
+  // windows of kernel 1 1^T contribute the sum of v
+  constexpr int kWinCache = 64;
+  __shared__ const T* s_y[kWinCache];
+  __shared__ double s_w[kWinCache];
+  const int nw = l1 - l0;
+  const bool cached = nw <= kWinCache;
+  if (cached && (int)threadIdx.x < nw) {
+    const WinDev& wl = wins[l0 + threadIdx.x];
+    s_w[threadIdx.x] = wl.weight;
+    s_y[threadIdx.x] = wl.t > 0 ? reinterpret_cast<const T*>(wl.ylocal) : nullptr;
+  }
+  __syncthreads();
+  const double sumv = *im.sumv;
   for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < N;
        i += (long long)nb * kRedThreads) {
     double y = 0.0;
-    for (int l = l0; l < l1; ++l)
-      y += wins[l].weight *
-           (wins[l].t > 0 ? (double)reinterpret_cast<const T*>(wins[l].ylocal)[i] : *im.sumv);
+    if (cached) {
+      for (int l = 0; l < nw; ++l) {
+        const T* yl = s_y[l];
+        y += s_w[l] * (yl ? (double)yl[i] : sumv);
+      }
+    } else {
+      for (int l = l0; l < l1; ++l)
+        y += wins[l].weight *
+             (wins[l].t > 0 ? (double)reinterpret_cast<const T*>(wins[l].ylocal)[i] : sumv);
+    }
     switch (a.mode) {
       case EPI_ANOVA:
         vout<T>(im, a.out)[i] = (T)y;
