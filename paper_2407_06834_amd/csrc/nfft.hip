@@ -1059,7 +1059,22 @@ k_reduce(const WinDev* __restrict__ wins, const ImgDev* __restrict__ imgs, Reduc
        i += (long long)nb * kRedThreads) {
     double y = 0.0;
     if (cached) {
-      for (int l = 0; l < nw; ++l) {
+      // eight windows' loads in flight at a time, summed in window order; a window of kernel
+      // 1 1^T loads from the input (any valid address) and takes the sum of v instead
+      int l = 0;
+      for (; l + 8 <= nw; l += 8) {
+        double t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const T* yl = s_y[l + k];
+          const GlobalPtr<T> src = (GlobalPtr<T>)(yl ? yl : v);
+          const double ld = (double)src[i];
+          t[k] = yl ? ld : sumv;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) y += s_w[l + k] * t[k];
+      }
+      for (; l < nw; ++l) {
         const T* yl = s_y[l];
         y += s_w[l] * (yl ? (double)yl[i] : sumv);
       }
