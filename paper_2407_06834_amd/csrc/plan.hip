@@ -436,9 +436,24 @@ static void upload_tables(Plan& P, std::vector<T>& coef_all, std::vector<T>& coe
                           hipStream_t s) {
   const int L = P.L, n_max = P.n_max;
   P.coef_host.assign(L, {});
+  // the window's Fourier factor depends on (n, m, b) only (b fixes M / n): evaluated once per
+  // distinct triple
+  std::vector<double> ph_tab;
+  int ph_n = -1, ph_m = -1;
+  double ph_b = 0.0;
   for (int l = 0; l < L; ++l) {
     const WinDev& w = P.wins[l];
     const int n = P.info[l].grid, M = P.info[l].bandwidth;
+    if (n != ph_n || w.m != ph_m || w.b != ph_b) {
+      ph_n = n;
+      ph_m = w.m;
+      ph_b = w.b;
+      ph_tab.assign(n, 0.0);
+      for (int q = 0; q < n; ++q) {
+        const int kf = (q < n / 2) ? q : q - n;
+        if (std::abs(kf) <= M / 2 - 1) ph_tab[q] = kb_fourier(kf, n, w.m, w.b);
+      }
+    }
     std::vector<double> coef(3LL * n, 0.0);
     for (int dd = 0; dd < 3; ++dd) {
       if (w.n[dd] == 1) continue;
@@ -447,7 +462,7 @@ static void upload_tables(Plan& P, std::vector<T>& coef_all, std::vector<T>& coe
         const int kf = (q < n / 2) ? q : q - n;
         if (std::abs(kf) <= M / 2 - 1) {
           const double bh = std::sqrt(M_PI) * st * std::exp(-std::pow(M_PI * st * kf, 2));
-          const double ph = kb_fourier(kf, n, w.m, w.b);
+          const double ph = ph_tab[q];
           coef[(long long)dd * n + q] = bh / (ph * ph);
         }
       }
@@ -682,10 +697,17 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     const int W = 2 * P.wins[0].m;
     psi_all.assign((size_t)L * W * (deg + 1), (T)0);
     P.psi_err = 0.0;
+    std::vector<double> c;                    // fitted once per distinct window shape (m, b)
+    int c_m = -1;
+    double c_b = 0.0;
     for (int l = 0; l < L; ++l) {
       double err = 0.0;
-      const std::vector<double> c = fit_window(P.wins[l].m, P.wins[l].b, deg, &err);
-      P.psi_err = std::max(P.psi_err, err);
+      if (P.wins[l].m != c_m || P.wins[l].b != c_b) {
+        c = fit_window(P.wins[l].m, P.wins[l].b, deg, &err);
+        c_m = P.wins[l].m;
+        c_b = P.wins[l].b;
+        P.psi_err = std::max(P.psi_err, err);
+      }
       for (size_t q = 0; q < c.size(); ++q) psi_all[(size_t)l * W * (deg + 1) + q] = (T)c[q];
     }
     P.psi = dalloc<T>((long long)psi_all.size(), s);
