@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 
 #include "nld_internal.h"
@@ -1011,7 +1012,26 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   P.have_D = false;
 }
 
+// Plans take their buffers from the device's stream-ordered pool (hipMallocAsync).  The pool's
+// default release threshold of zero hands freed memory back at every synchronisation, so a
+// new plan (with slot buffers of up to a few hundred MB) would map it again; the library keeps
+// it in the pool instead, for the life of the process, once per device.
+static void keep_pool_memory() {
+  static std::mutex mu;
+  static bool done[64] = {};
+  int dev = 0;
+  NLD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev < 0 || dev >= 64 || done[dev]) return;
+  hipMemPool_t pool;
+  NLD_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t keep = ~0ULL;
+  NLD_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  done[dev] = true;
+}
+
 void build_plan(Plan& P, const void* features, hipStream_t s) {
+  keep_pool_memory();
   P.features = const_cast<void*>(features);
   P.stream = s;
   if (P.prec == NLD_FP32) build_plan_t<float>(P, features, s);
