@@ -24,27 +24,46 @@ __device__ __forceinline__ double kb_psi(double delta, double m, double b, doubl
   return 2.0 * b * m * exp(-b * m) * den;
 }
 
-// Deterministic FP64 reduction of NS values over the whole grid: every block reduces its
-// threads' values with a fixed tree, writes one partial per value, and the last block to
-// finish (agent-scope ticket) sums the partials in block order.  Returns true in the last
-// block, with the totals in out[] for every thread of that block.  Block size must be
-// kRedThreads; nblocks blocks (blockIdx.x < nblocks) take part; the ticket is reset by the
-// last block.
+// Sum of NS values over a block of kRedThreads threads, the same bits in every thread: an XOR
+// butterfly within each wavefront (each step adds symmetric pairs, so all lanes agree), then
+// the wavefronts' partials in order.
+template <int NS>
+__device__ __forceinline__ void block_sum(double (&v)[NS]) {
+  constexpr int kWaves = kRedThreads / 64;
+  __shared__ double sh[NS][kWaves];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) v[k] += __shfl_xor(v[k], off);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) sh[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    double s = sh[k][0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) s += sh[k][w];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// Deterministic FP64 reduction of NS values over the whole grid: every block sums its threads'
+// values in a fixed order, writes one partial per value, and the last block to finish
+// (agent-scope ticket) sums the partials in block order.  Returns true in the last block, with
+// the totals in out[] for every thread of that block.  Block size must be kRedThreads;
+// nblocks blocks (blockIdx.x < nblocks) take part; the ticket is reset by the last block.
 template <int NS>
 __device__ bool grid_reduce(const double (&v)[NS], double* red, unsigned* ticket,
                             double (&out)[NS], unsigned nblocks) {
-  __shared__ double sh[NS][kRedThreads];
   __shared__ int last;
   const int t = threadIdx.x;
-  for (int k = 0; k < NS; ++k) sh[k][t] = v[k];
-  __syncthreads();
-  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-    if (t < s)
-      for (int k = 0; k < NS; ++k) sh[k][t] += sh[k][t + s];
-    __syncthreads();
-  }
+  double bs[NS];
+  for (int k = 0; k < NS; ++k) bs[k] = v[k];
+  block_sum<NS>(bs);
   if (t == 0) {
-    for (int k = 0; k < NS; ++k) red[(size_t)blockIdx.x * 8 + k] = sh[k][0];
+    for (int k = 0; k < NS; ++k) red[(size_t)blockIdx.x * 8 + k] = bs[k];
     __threadfence();
     const unsigned prev = atomicAdd(ticket, 1u);
     last = (prev == nblocks - 1) ? 1 : 0;
@@ -58,15 +77,8 @@ __device__ bool grid_reduce(const double (&v)[NS], double* red, unsigned* ticket
     for (int k = 0; k < NS; ++k)
       acc[k] += __hip_atomic_load(&red[(size_t)b * 8 + k], __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  for (int k = 0; k < NS; ++k) sh[k][t] = acc[k];
-  __syncthreads();
-  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-    if (t < s)
-      for (int k = 0; k < NS; ++k) sh[k][t] += sh[k][t + s];
-    __syncthreads();
-  }
-  for (int k = 0; k < NS; ++k) out[k] = sh[k][0];
+  block_sum<NS>(acc);
+  for (int k = 0; k < NS; ++k) out[k] = acc[k];
   if (t == 0) atomicExch(ticket, 0u);
   return true;
 }
