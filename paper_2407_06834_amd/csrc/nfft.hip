@@ -206,6 +206,10 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   // and the first dimension's W weights are broadcast to every lane.
   static_assert(TD * W <= 64, "one lane per tap and dimension");
   const int my_tap = lane % W, my_dim = lane / W;   // lanes with my_dim >= TD idle here
+  // x = 2 f - 1 of this lane's dimension as three FMAs with per-lane factors 2 or 0 (a node's
+  // fractions are wave-uniform scalars): the same rounding as 2 f - 1, no selects
+  const T sel0 = my_dim == 0 ? (T)2 : (T)0, sel1 = my_dim == 1 ? (T)2 : (T)0,
+          sel2 = my_dim == 2 ? (T)2 : (T)0;
   T cf[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) cf[q] = psi[my_tap * K + q];
@@ -282,17 +286,18 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
         cur = bq;
       }
       const T vq = lane_bcast(vv, q);
-      T fsel;
+      T xsel;
       if constexpr (TD == 3) {
-        const T fa = lane_bcast(f0, q), fb = lane_bcast(f1, q), fc = lane_bcast(f2, q);
-        fsel = (my_dim == 0) ? fa : (my_dim == 1) ? fb : fc;
+        xsel = fma(lane_bcast(f0, q), sel0, (T)-1);
+        xsel = fma(lane_bcast(f1, q), sel1, xsel);
+        xsel = fma(lane_bcast(f2, q), sel2, xsel);
       } else if constexpr (TD == 2) {
-        const T fb = lane_bcast(f1, q), fc = lane_bcast(f2, q);
-        fsel = (my_dim == 0) ? fb : fc;
+        xsel = fma(lane_bcast(f1, q), sel0, (T)-1);
+        xsel = fma(lane_bcast(f2, q), sel1, xsel);
       } else {
-        fsel = lane_bcast(f2, q);
+        xsel = fma(lane_bcast(f2, q), sel0, (T)-1);
       }
-      const T wv = horner<T, K>(cf, (T)2 * fsel - (T)1);
+      const T wv = horner<T, K>(cf, xsel);
       T w12[NP];
 #pragma unroll
       for (int k = 0; k < NP; ++k) {
