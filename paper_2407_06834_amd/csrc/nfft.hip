@@ -140,7 +140,10 @@ __device__ __forceinline__ void poly_row(P psi, T fr, T* wt) {
 // the lanes' 8-byte addresses meet in fewer LDS banks.)
 // The slot is then written back in the working precision, in the slot layout above; the fold
 // kernel sums the slots that cover each grid cell.
-template <typename T, int W, int TD>
+// TSC = 8: every 3-D window of the launch has 8^3 tiles, so the padded extents and strides are
+// compile-time constants (LDS offsets fold into the instructions); TSC = 0 reads them from the
+// window descriptor.
+template <typename T, int W, int TD, int TSC>
 __global__ void __launch_bounds__(kSpreadThreads)
 k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int job0,
          const ImgDev* __restrict__ imgs, VecArg in, int check) {
@@ -173,8 +176,9 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   Acc* acc = reinterpret_cast<Acc*>(smem_raw);
   Acc* acc_lo = acc + (kTwo ? w.pe[0] * w.pe[1] * w.pe[2] : 0);
   __shared__ double s_part[kSpreadWaves];
-  const int pe1 = w.pe[1], pe2 = w.pe[2];
-  const int cells = w.pe[0] * pe1 * pe2;
+  constexpr int PEC = (TD == 3 && TSC > 0) ? TSC + W - 1 : 0;
+  const int pe1 = PEC ? PEC : w.pe[1], pe2 = PEC ? PEC : w.pe[2];
+  const int cells = PEC ? PEC * PEC * PEC : w.pe[0] * pe1 * pe2;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wavefront
   GlobalPtr<T> psi = (GlobalPtr<T>)w.psi;
@@ -324,7 +328,7 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   // the two FP32 words combine exactly in double (at most 50 significant bits)
   const double inv = kTwo ? 1.0 / (scale * (double)kLoScale) : 1.0 / scale;
   // a thread owns columns (x1, x2) of the padded tile and walks them along the first dimension
-  const int pe0 = w.pe[0], a0 = w.taps[0] > 1 ? w.m - 1 : 0;
+  const int pe0 = PEC ? PEC : w.pe[0], a0 = w.taps[0] > 1 ? w.m - 1 : 0;
   const int a1 = w.taps[1] > 1 ? w.m - 1 : 0, a2 = w.taps[2] > 1 ? w.m - 1 : 0;
   for (int col = threadIdx.x; col < s01; col += kSpreadThreads) {
     const int x1 = col / pe2, x2 = col - x1 * pe2;
@@ -881,7 +885,7 @@ k_plane(const WinDev* __restrict__ wins, const PlaneJob* __restrict__ jobs, int 
 // of the node loop, so the staged one reads through an LDS pointer (ds_read) rather than a
 // generic one (flat loads).
 
-template <typename T, int W, int TD, bool STAGED, typename PP>
+template <typename T, int W, int TD, bool STAGED, int TSC, typename PP>
 __device__ __forceinline__ void gather_nodes(const TileJob& job, const WinDev& w,
                                              const T* __restrict__ tile, const T* __restrict__ h,
                                              PP psi, int o0, int o1, int o2) {
@@ -896,7 +900,8 @@ __device__ __forceinline__ void gather_nodes(const TileJob& job, const WinDev& w
   const long long LN = w.LN;
   T* __restrict__ ylocal = reinterpret_cast<T*>(w.ylocal);
   const int n0 = w.n[0], n1 = w.n[1], n2 = w.n[2];
-  const int pe1 = w.pe[1], pe2 = w.pe[2];
+  constexpr int PEC = (TD == 3 && TSC > 0) ? TSC + W - 1 : 0;
+  const int pe1 = PEC ? PEC : w.pe[1], pe2 = PEC ? PEC : w.pe[2];
   // explicit address spaces: LDS reads for the staged tile, global loads otherwise
   LdsPtr<T> tile_l = (LdsPtr<T>)tile;
   GlobalPtr<T> h_g = (GlobalPtr<T>)h;
@@ -950,7 +955,7 @@ __device__ __forceinline__ void gather_nodes(const TileJob& job, const WinDev& w
   }
 }
 
-template <typename T, int W, int TD>
+template <typename T, int W, int TD, int TSC>
 __global__ void __launch_bounds__(kGatherThreads)
 k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int job0,
          const ImgDev* __restrict__ imgs, int check, int stage_min) {
@@ -961,7 +966,8 @@ k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   T* tile = reinterpret_cast<T*>(smem_raw);
   const T* h = reinterpret_cast<const T*>(w.grid) + w.grid_off;
   const int n0 = w.n[0], n1 = w.n[1], n2 = w.n[2];
-  const int pe0 = w.pe[0], pe1 = w.pe[1], pe2 = w.pe[2];
+  constexpr int PEC = (TD == 3 && TSC > 0) ? TSC + W - 1 : 0;
+  const int pe0 = PEC ? PEC : w.pe[0], pe1 = PEC ? PEC : w.pe[1], pe2 = PEC ? PEC : w.pe[2];
   const int o0 = tile_origin(w, job.tile, 0), o1 = tile_origin(w, job.tile, 1),
             o2 = tile_origin(w, job.tile, 2);
   constexpr int m = W / 2;
@@ -989,14 +995,14 @@ k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
         tile[a0 * s01 + col] = h[(long long)((s0 + a0) & (n0 - 1)) * n1 * n2 + row];
     }
     __syncthreads();
-    if constexpr (PSI_LDS) gather_nodes<T, W, TD, true>(job, w, tile, h, (LdsPtr<T>)s_psi, o0, o1, o2);
-    else gather_nodes<T, W, TD, true>(job, w, tile, h, (ConstPtr<T>)psi_g, o0, o1, o2);
+    if constexpr (PSI_LDS) gather_nodes<T, W, TD, true, TSC>(job, w, tile, h, (LdsPtr<T>)s_psi, o0, o1, o2);
+    else gather_nodes<T, W, TD, true, TSC>(job, w, tile, h, (ConstPtr<T>)psi_g, o0, o1, o2);
   } else {
     if constexpr (PSI_LDS) {
       __syncthreads();
-      gather_nodes<T, W, TD, false>(job, w, tile, h, (LdsPtr<T>)s_psi, o0, o1, o2);
+      gather_nodes<T, W, TD, false, TSC>(job, w, tile, h, (LdsPtr<T>)s_psi, o0, o1, o2);
     } else {
-      gather_nodes<T, W, TD, false>(job, w, tile, h, (ConstPtr<T>)psi_g, o0, o1, o2);
+      gather_nodes<T, W, TD, false, TSC>(job, w, tile, h, (ConstPtr<T>)psi_g, o0, o1, o2);
     }
   }
 }
@@ -1175,13 +1181,16 @@ void launch_tiles(const LaunchSet& ls, VecArg in, int check, hipStream_t s, bool
   for (int g = 0; g < 3; ++g) {
     const int j0 = ls.tjob_begin[g], nj = ls.tjob_begin[g + 1] - j0;
     if (nj == 0) continue;
+    const bool c8 = ls.ts3 == 8;
     if (!gather) {
-      auto k = (g == 0) ? k_spread<T, W, 1> : (g == 1) ? k_spread<T, W, 2> : k_spread<T, W, 3>;
+      auto k = (g == 0) ? k_spread<T, W, 1, 0> : (g == 1) ? k_spread<T, W, 2, 0>
+             : c8 ? k_spread<T, W, 3, 8> : k_spread<T, W, 3, 0>;
       allow_lds(k, lds);
       hipLaunchKernelGGL(k, dim3(nj), dim3(kSpreadThreads), lds, s, ls.d_wins, ls.d_tjobs, j0,
                          ls.d_imgs, in, check);
     } else {
-      auto k = (g == 0) ? k_gather<T, W, 1> : (g == 1) ? k_gather<T, W, 2> : k_gather<T, W, 3>;
+      auto k = (g == 0) ? k_gather<T, W, 1, 0> : (g == 1) ? k_gather<T, W, 2, 0>
+             : c8 ? k_gather<T, W, 3, 8> : k_gather<T, W, 3, 0>;
       allow_lds(k, lds);
       hipLaunchKernelGGL(k, dim3(nj), dim3(kGatherThreads), lds, s, ls.d_wins, ls.d_tjobs, j0,
                          ls.d_imgs, check, gather_stage_min());

@@ -136,6 +136,7 @@ struct LaunchSet {
   const TileJob* d_tjobs = nullptr;
   int tjob_begin[4] = {0, 0, 0, 0};             // group g: windows with t = g + 1
   int max_padded = 1;                           // largest padded tile (cells)
+  int ts3 = 0;                                  // 8 if every 3-D window has 8^3 tiles, else 0
   const Fold3Job* d_f3jobs = nullptr;
   int f3_begin[3] = {0, 0, 0};                  // tile extent 8: [0], [1]); 16: [1], [2])
   const FoldJob* d_fjobs = nullptr;

@@ -973,6 +973,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   ls.d_tjobs = P.d_tjobs;
   for (int g = 0; g < 4; ++g) ls.tjob_begin[g] = P.tjob_begin[g];
   ls.max_padded = P.max_padded;
+  ls.ts3 = (P.f3_ts == 8) ? 8 : 0;
   ls.d_f3jobs = P.d_f3jobs;
   ls.f3_begin[0] = 0;
   ls.f3_begin[1] = (P.f3_ts == 16) ? 0 : P.n_f3jobs;
