@@ -469,27 +469,33 @@ k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int 
     g[((long long)(o0 + x0) * w.n[1] + (o1 + x1)) * w.n[2] + (o2 + x2)] = acc[x0];
 }
 
-// Fold of a 3-D window with 8^3 tiles and cutoff M known at compile time, one wavefront per
-// tile.  Each of the 27 neighbours contributes one block of its slot (the slot layout stores it
-// contiguously): the wavefront reads the block with consecutive lanes on consecutive cells and
-// adds it into the tile held in LDS, neighbour after neighbour and slot after slot, the order of
-// k_fold3 (so the same sums bit for bit).  Block shapes and positions are compile-time
-// constants; the lanes of one block hit distinct cells, and one wavefront keeps the LDS
-// updates in order.
-template <typename T, int M>
-__global__ void __launch_bounds__(64)
+// Fold of a 3-D window with 8^3 tiles and cutoff M known at compile time.  A workgroup of Q
+// wavefronts (Q = 1 or 4) takes Q consecutive jobs; with Q = 4 they are the same window's tiles
+// t2 = 4g .. 4g + 3 (jobs list every tile of a window in order, and Q = 4 is used only when
+// every window has a multiple of four tiles along the last dimension).  Each wavefront folds
+// one tile.  Each of the 27 neighbours contributes one
+// block of its slot (the slot layout stores it contiguously): the wavefront reads the block
+// with consecutive lanes on consecutive cells and adds it into its tile in LDS, neighbour after
+// neighbour and slot after slot, the order of k_fold3 (so the same sums bit for bit).  Block
+// shapes and positions are compile-time constants; the lanes of one block hit distinct cells,
+// and one wavefront keeps its LDS updates in order.  The Q tiles are then written together,
+// rows of 8 Q cells along the contiguous dimension (128 bytes for Q = 4 in FP32).
+template <typename T, int M, int Q>
+__global__ void __launch_bounds__(64 * Q)
 k_fold3m(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int job0,
          const ImgDev* __restrict__ imgs, int check) {
   constexpr int TS = 8, LEFT = M - 1, PE = TS + 2 * M - 1;
-  __shared__ T tile[TS * TS * TS];
-  const Fold3Job job = jobs[job0 + blockIdx.x];
+  __shared__ T tiles[Q][TS * TS * TS];
+  const int wave = Q == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const Fold3Job job = jobs[job0 + Q * blockIdx.x + wave];
   const WinDev& w = wins[job.win];
-  if (check && imgs[w.img].st->done) return;
+  if (check && imgs[w.img].st->done) return;            // the same image for the Q jobs
+  T* tile = tiles[wave];
   GlobalPtr<T> padded = (GlobalPtr<T>)w.padded;
   const long long slot_stride = w.slot_stride;
   ConstPtr<int> tile_slot0 = (ConstPtr<int>)w.tile_slot0;
   ConstPtr<int> tile_nslot = (ConstPtr<int>)w.tile_nslot;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const int tc2 = job.tile & (w.nts[2] - 1);
   const int tc1 = (job.tile >> w.lnts[2]) & (w.nts[1] - 1);
   const int tc0 = job.tile >> (w.lnts[2] + w.lnts[1]);
@@ -552,12 +558,17 @@ k_fold3m(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int
   if (!multi) static_for<27>([&](auto n_c) { fold_block(n_c, std::false_type{}); });
   else static_for<27>([&](auto n_c) { fold_block(n_c, std::true_type{}); });
   __syncthreads();
+  // rows (x0, x1) of the Q tiles: 8 Q consecutive cells from the first tile's origin
   T __attribute__((address_space(1)))* g = (T __attribute__((address_space(1)))*)w.grid + w.grid_off;
-  const int o0 = tc0 * TS, o1 = tc1 * TS, o2 = tc2 * TS;
-  const int x2 = lane % TS, x1 = lane / TS;
+  const int o0 = tc0 * TS, o1 = tc1 * TS, o2 = (tc2 & ~(Q - 1)) * TS;
 #pragma unroll
-  for (int x0 = 0; x0 < TS; ++x0)
-    g[((long long)(o0 + x0) * w.n[1] + (o1 + x1)) * w.n[2] + (o2 + x2)] = tile[(x0 * TS + x1) * TS + x2];
+  for (int it = 0; it < TS; ++it) {
+    const int idx = threadIdx.x + 64 * Q * it;
+    const int col = idx % (Q * TS), row = idx / (Q * TS);   // row = x0 * TS + x1
+    const int x0 = row / TS, x1 = row % TS;
+    g[((long long)(o0 + x0) * w.n[1] + (o1 + x1)) * w.n[2] + (o2 + col)] =
+        tiles[col / TS][(x0 * TS + x1) * TS + (col % TS)];
+  }
 }
 
 // ---------------------------------------------------------------------------- convolution
@@ -1265,11 +1276,21 @@ void spread_fold(const LaunchSet& ls, VecArg in, int check, hipStream_t s) {
   tiles_dispatch<T>(ls, in, check, s, false);
   const int n8 = ls.f3_begin[1] - ls.f3_begin[0], n16 = ls.f3_begin[2] - ls.f3_begin[1];
   if (n8 > 0) {
-    auto k = (ls.m == 1) ? k_fold3m<T, 1> : (ls.m == 2) ? k_fold3m<T, 2> : (ls.m == 3) ? k_fold3m<T, 3>
-           : (ls.m == 4) ? k_fold3m<T, 4> : (ls.m == 5) ? k_fold3m<T, 5> : (ls.m == 6) ? k_fold3m<T, 6>
-           : (ls.m == 7) ? k_fold3m<T, 7> : k_fold3m<T, 8>;
-    hipLaunchKernelGGL(k, dim3(n8), dim3(64), 0, s, ls.d_wins, ls.d_f3jobs, ls.f3_begin[0],
-                       ls.d_imgs, check);
+    auto pick = [&](auto q) {
+      constexpr int Q = decltype(q)::value;
+      return (ls.m == 1) ? k_fold3m<T, 1, Q> : (ls.m == 2) ? k_fold3m<T, 2, Q>
+           : (ls.m == 3) ? k_fold3m<T, 3, Q> : (ls.m == 4) ? k_fold3m<T, 4, Q>
+           : (ls.m == 5) ? k_fold3m<T, 5, Q> : (ls.m == 6) ? k_fold3m<T, 6, Q>
+           : (ls.m == 7) ? k_fold3m<T, 7, Q> : k_fold3m<T, 8, Q>;
+    };
+    if (ls.f3_quad) {
+      if (n8 % 4 != 0) throw std::runtime_error("internal: 8^3 fold jobs not in groups of four");
+      hipLaunchKernelGGL(pick(std::integral_constant<int, 4>{}), dim3(n8 / 4), dim3(256), 0, s,
+                         ls.d_wins, ls.d_f3jobs, ls.f3_begin[0], ls.d_imgs, check);
+    } else {
+      hipLaunchKernelGGL(pick(std::integral_constant<int, 1>{}), dim3(n8), dim3(64), 0, s,
+                         ls.d_wins, ls.d_f3jobs, ls.f3_begin[0], ls.d_imgs, check);
+    }
   }
   if (n16 > 0)
     hipLaunchKernelGGL((k_fold3<T, 16>), dim3(n16), dim3(256), 0, s, ls.d_wins, ls.d_f3jobs,

@@ -137,6 +137,7 @@ struct LaunchSet {
   int tjob_begin[4] = {0, 0, 0, 0};             // group g: windows with t = g + 1
   int max_padded = 1;                           // largest padded tile (cells)
   int ts3 = 0;                                  // 8 if every 3-D window has 8^3 tiles, else 0
+  bool f3_quad = false;                         // every 8^3-tiled window: 4 | tiles along dim 2
   const Fold3Job* d_f3jobs = nullptr;
   int f3_begin[3] = {0, 0, 0};                  // tile extent 8: [0], [1]); 16: [1], [2])
   const FoldJob* d_fjobs = nullptr;
@@ -224,6 +225,7 @@ struct Plan {
   FoldJob* d_fjobs = nullptr; int n_fjobs = 0;     // per-cell fold (windows with t <= 2)
   Fold3Job* d_f3jobs = nullptr; int n_f3jobs = 0;   // per-tile fold (windows with t = 3)
   int f3_ts = 0;                                   // tile extent of the 3-D windows (8 or 16)
+  bool f3_quad = false;                            // 4 | tiles along dim 2 in every 3-D window
   // convolution jobs per axis, grouped by grid size n = 32, 64, 128, 256 (group g: n = 32 << g)
   ConvJob* d_conv[3] = {nullptr, nullptr, nullptr};
   int conv_begin[3][5] = {{0}};

@@ -471,6 +471,7 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
     ls.m = plans[0]->wins[0].m;
     ls.n_imgs = count;
     ls.ts3 = 8;                                   // unless a plan's 3-D windows use 16^3 tiles
+    ls.f3_quad = true;                            // unless a plan's 3-D windows break the groups
     CgState* d_st = nullptr;
     NLD_HIP(hipMallocAsync((void**)&d_st, (size_t)count * sizeof(CgState), cs));
     owned.push_back(d_st);
@@ -521,6 +522,7 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
       im.red = d_red + (size_t)b * kRedBlocks * 8;
       ls.max_padded = std::max(ls.max_padded, P.max_padded);
       if (P.f3_ts == 16) ls.ts3 = 0;
+      ls.f3_quad = ls.f3_quad && P.f3_quad;
       ls.max_N = std::max<long long>(ls.max_N, P.N);
       ls.max_nred = std::max(ls.max_nred, im.nred);
       ls.has_flat = ls.has_flat || P.has_flat;

@@ -807,12 +807,14 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   std::vector<FoldJob> fj;
   std::vector<Fold3Job> f3;
   P.f3_ts = 0;
+  P.f3_quad = true;
   for (int l = 0; l < L; ++l) {
     const WinDev& w = P.wins[l];
     if (w.t == 3) {
       if (P.f3_ts != 0 && P.f3_ts != w.ts[0]) throw std::runtime_error("internal: mixed 3-D tile sizes");
       if (w.ts[0] != w.ts[1] || w.ts[1] != w.ts[2]) throw std::runtime_error("internal: non-cubic tile");
       P.f3_ts = w.ts[0];
+      P.f3_quad = P.f3_quad && w.nts[2] % 4 == 0;
       const int nt = w.nts[0] * w.nts[1] * w.nts[2];
       for (int tl = 0; tl < nt; ++tl) f3.push_back(Fold3Job{l, tl});
     } else if (w.t > 0) {
@@ -974,6 +976,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   for (int g = 0; g < 4; ++g) ls.tjob_begin[g] = P.tjob_begin[g];
   ls.max_padded = P.max_padded;
   ls.ts3 = (P.f3_ts == 8) ? 8 : 0;
+  ls.f3_quad = P.f3_quad;
   ls.d_f3jobs = P.d_f3jobs;
   ls.f3_begin[0] = 0;
   ls.f3_begin[1] = (P.f3_ts == 16) ? 0 : P.n_f3jobs;
