@@ -478,18 +478,50 @@ k_fold3(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int 
 // with consecutive lanes on consecutive cells and adds it into its tile in LDS, neighbour after
 // neighbour and slot after slot, the order of k_fold3 (so the same sums bit for bit).  Block
 // shapes and positions are compile-time constants; the lanes of one block hit distinct cells,
-// and one wavefront keeps its LDS updates in order.  The Q tiles are then written together,
-// rows of 8 Q cells along the contiguous dimension (128 bytes for Q = 4 in FP32).
+// and one wavefront keeps its LDS updates in order.  When every neighbour has at most one slot,
+// the loads of a group of blocks (all 27, or the 9 of one offset d0 for large M) are issued
+// before any of their additions, so a wavefront waits on memory once per group rather than once
+// per block.  The Q tiles are then written together, rows of 8 Q cells along the contiguous
+// dimension (128 bytes for Q = 4 in FP32).
+template <int M>
+struct Fold8Geo {
+  static constexpr int TS = 8, LEFT = M - 1, PE = TS + 2 * M - 1;
+  // Neighbour offset d along a dimension selects the block of its slot that folds into this
+  // tile: d = -1 its right part (M cells, padded start LEFT + TS) onto cells [0, M), d = 0 the
+  // tile part (TS cells, start LEFT) onto [0, TS), d = +1 its left part (M - 1 cells, start 0)
+  // onto [TS - LEFT, TS).
+  static constexpr int pre(int d) { return d < 0 ? LEFT + TS : (d == 0 ? LEFT : 0); }
+  static constexpr int sz(int d) { return d < 0 ? M : (d == 0 ? TS : LEFT); }
+  static constexpr int off(int d) { return d > 0 ? TS - LEFT : 0; }
+  static constexpr int d0(int n) { return n / 9 - 1; }
+  static constexpr int d1(int n) { return (n / 3) % 3 - 1; }
+  static constexpr int d2(int n) { return n % 3 - 1; }
+  static constexpr int bs(int n) { return sz(d0(n)) * sz(d1(n)) * sz(d2(n)); }
+  static constexpr int nit(int n) { return (bs(n) + 63) / 64; }       // loads per lane
+  static constexpr int first(int n) {                                 // registers before block n
+    int s = 0;
+    for (int k = 0; k < n; ++k) s += nit(k);
+    return s;
+  }
+  static constexpr int group = first(27) <= 96 ? 27 : 9;              // blocks loaded together
+  static constexpr int base(int n) {                                  // block start in the slot
+    return pre(d0(n)) * PE * PE + sz(d0(n)) * (pre(d1(n)) * PE + sz(d1(n)) * pre(d2(n)));
+  }
+};
+
 template <typename T, int M, int Q>
 __global__ void __launch_bounds__(64 * Q)
 k_fold3m(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int job0,
          const ImgDev* __restrict__ imgs, int check) {
-  constexpr int TS = 8, LEFT = M - 1, PE = TS + 2 * M - 1;
+  constexpr int TS = 8;
   __shared__ T tiles[Q][TS * TS * TS];
   const int wave = Q == 1 ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const Fold3Job job = jobs[job0 + Q * blockIdx.x + wave];
   const WinDev& w = wins[job.win];
-  if (check && imgs[w.img].st->done) return;            // the same image for the Q jobs
+  // The image's finished flag is read after the block loads are issued (the same image for the
+  // Q jobs), so its two dependent loads overlap the slot tables and the slot data; a finished
+  // image's slots are read but never used.
+  const CgState* st = imgs[w.img].st;
   T* tile = tiles[wave];
   GlobalPtr<T> padded = (GlobalPtr<T>)w.padded;
   const long long slot_stride = w.slot_stride;
@@ -499,64 +531,94 @@ k_fold3m(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int
   const int tc2 = job.tile & (w.nts[2] - 1);
   const int tc1 = (job.tile >> w.lnts[2]) & (w.nts[1] - 1);
   const int tc0 = job.tile >> (w.lnts[2] + w.lnts[1]);
-  // slot tables of the 27 neighbours (uniform)
-  int ns[27], s0t[27];
-#pragma unroll
-  for (int n = 0; n < 27; ++n) {
-    const int d0 = n / 9 - 1, d1 = (n / 3) % 3 - 1, d2 = n % 3 - 1;
+  // slot tables of the 27 neighbours: lane n < 27 loads neighbour n's entries (one round trip
+  // of vector loads rather than a chain of scalar ones), then every lane reads them (uniform)
+  int my_ns = 0, my_s0 = 0;
+  if (lane < 27) {
+    const int d0 = lane / 9 - 1, d1 = (lane / 3) % 3 - 1, d2 = lane % 3 - 1;
     const int t0 = (tc0 + d0) & (w.nts[0] - 1), t1 = (tc1 + d1) & (w.nts[1] - 1),
               t2 = (tc2 + d2) & (w.nts[2] - 1);
     const int gt = w.tile_off + (((t0 << w.lnts[1]) + t1) << w.lnts[2]) + t2;
-    ns[n] = tile_nslot[gt];
-    s0t[n] = tile_slot0[gt];
+    my_ns = tile_nslot[gt];
+    my_s0 = tile_slot0[gt];
+  }
+  int ns[27], s0t[27];
+#pragma unroll
+  for (int n = 0; n < 27; ++n) {
+    ns[n] = __builtin_amdgcn_readlane(my_ns, n);
+    s0t[n] = __builtin_amdgcn_readlane(my_s0, n);
   }
 #pragma unroll
   for (int k = 0; k < TS * TS * TS / 64; ++k) tile[lane + 64 * k] = (T)0;
   bool multi = false;
 #pragma unroll
   for (int n = 0; n < 27; ++n) multi = multi || ns[n] > 1;
-  // Neighbour offset d along a dimension selects the block of its slot that folds into this
-  // tile: d = -1 its right part (M cells, padded start LEFT + TS) onto cells [0, M), d = 0 the
-  // tile part (TS cells, start LEFT) onto [0, TS), d = +1 its left part (M - 1 cells, start 0)
-  // onto [TS - LEFT, TS).
-  constexpr auto pre = [](int d) { return d < 0 ? LEFT + TS : (d == 0 ? LEFT : 0); };
-  constexpr auto sz = [](int d) { return d < 0 ? M : (d == 0 ? TS : LEFT); };
-  constexpr auto off = [](int d) { return d > 0 ? TS - LEFT : 0; };
-  // one neighbour's block: load (one slot, or the sum of its slots in order), then add
-  auto fold_block = [&](auto n_c, auto multi_c) {
+  using G = Fold8Geo<M>;
+  // one neighbour's block (lanes past the block reread cell 0), added into the tile
+  auto add_block = [&](auto n_c, const T* val) {
     constexpr int n = decltype(n_c)::value;
-    constexpr bool MULTI = decltype(multi_c)::value;
-    constexpr int d0 = n / 9 - 1, d1 = (n / 3) % 3 - 1, d2 = n % 3 - 1;
-    constexpr int sz0 = sz(d0), sz1 = sz(d1), sz2 = sz(d2), bs = sz0 * sz1 * sz2;
-    constexpr int nit = (bs + 63) / 64;
-    if constexpr (bs > 0) {
-      if (ns[n] == 0) return;                                 // uniform: empty neighbour tile
-      constexpr int base = pre(d0) * PE * PE + sz0 * (pre(d1) * PE + sz1 * pre(d2));
-      const long long src = (long long)s0t[n] * slot_stride + base;
-      T val[nit];
+    constexpr int sz1 = G::sz(G::d1(n)), sz2 = G::sz(G::d2(n));
 #pragma unroll
-      for (int it = 0; it < nit; ++it) {
-        const int e = lane + 64 * it;
-        const int ec = e < bs ? e : 0;                        // lanes past the block reread cell 0
-        if constexpr (!MULTI) {
-          val[it] = padded[src + ec];
-        } else {
+    for (int it = 0; it < G::nit(n); ++it) {
+      const int e = lane + 64 * it;
+      if (e >= G::bs(n)) continue;
+      const int r2 = e % sz2, r1 = (e / sz2) % sz1, r0 = e / (sz1 * sz2);
+      tile[((r0 + G::off(G::d0(n))) * TS + (r1 + G::off(G::d1(n)))) * TS + (r2 + G::off(G::d2(n)))] +=
+          val[it];
+    }
+  };
+  bool finished = false;
+  if (!multi) {
+    // groups of blocks: every load of the group, then the additions in neighbour order
+    static_for<27 / G::group>([&](auto g_c) {
+      if (finished) return;
+      constexpr int n0 = decltype(g_c)::value * G::group, v0 = G::first(n0);
+      T val[G::first(n0 + G::group) - v0];
+      static_for<G::group>([&](auto k_c) {
+        constexpr int n = n0 + decltype(k_c)::value;
+        if constexpr (G::bs(n) > 0) {
+          if (ns[n] != 0) {                                   // uniform: empty neighbour tile
+            const long long src = (long long)s0t[n] * slot_stride + G::base(n);
+#pragma unroll
+            for (int it = 0; it < G::nit(n); ++it) {
+              const int e = lane + 64 * it;
+              val[G::first(n) - v0 + it] = padded[src + (e < G::bs(n) ? e : 0)];
+            }
+          }
+        }
+      });
+      if (decltype(g_c)::value == 0 && check && st->done) {
+        finished = true;
+        return;
+      }
+      static_for<G::group>([&](auto k_c) {
+        constexpr int n = n0 + decltype(k_c)::value;
+        if constexpr (G::bs(n) > 0)
+          if (ns[n] != 0) add_block(std::integral_constant<int, n>{}, val + (G::first(n) - v0));
+      });
+    });
+  } else {
+    finished = check && st->done;
+    // some neighbour has several slots: each block is the sum of its slots in order
+    if (!finished) static_for<27>([&](auto n_c) {
+      constexpr int n = decltype(n_c)::value;
+      if constexpr (G::bs(n) > 0) {
+        if (ns[n] == 0) return;                               // uniform: empty neighbour tile
+        const long long src = (long long)s0t[n] * slot_stride + G::base(n);
+        T val[G::nit(n)];
+#pragma unroll
+        for (int it = 0; it < G::nit(n); ++it) {
+          const int e = lane + 64 * it;
+          const int ec = e < G::bs(n) ? e : 0;
           T sum = (T)0;
           for (int k = 0; k < ns[n]; ++k) sum += padded[src + (long long)k * slot_stride + ec];
           val[it] = sum;
         }
+        add_block(n_c, val);
       }
-#pragma unroll
-      for (int it = 0; it < nit; ++it) {
-        const int e = lane + 64 * it;
-        if (e >= bs) continue;
-        const int r2 = e % sz2, r1 = (e / sz2) % sz1, r0 = e / (sz1 * sz2);
-        tile[((r0 + off(d0)) * TS + (r1 + off(d1))) * TS + (r2 + off(d2))] += val[it];
-      }
-    }
-  };
-  if (!multi) static_for<27>([&](auto n_c) { fold_block(n_c, std::false_type{}); });
-  else static_for<27>([&](auto n_c) { fold_block(n_c, std::true_type{}); });
+    });
+  }
+  if (finished) return;                                   // uniform over the workgroup
   __syncthreads();
   // rows (x0, x1) of the Q tiles: 8 Q consecutive cells from the first tile's origin
   T __attribute__((address_space(1)))* g = (T __attribute__((address_space(1)))*)w.grid + w.grid_off;
