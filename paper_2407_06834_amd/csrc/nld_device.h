@@ -83,13 +83,6 @@ __device__ bool grid_reduce(const double (&v)[NS], double* red, unsigned* ticket
   return true;
 }
 
-inline unsigned red_blocks(long long n) {
-  long long b = (n + kRedThreads - 1) / kRedThreads;
-  if (b > kRedBlocks) b = kRedBlocks;
-  if (b < 1) b = 1;
-  return (unsigned)b;
-}
-
 template <typename T>
 __device__ __forceinline__ const T* vin(const ImgDev& im, VecArg a) {
   return a.ext ? reinterpret_cast<const T*>(a.ext) : reinterpret_cast<const T*>(im.vec[a.sel]);

@@ -945,7 +945,10 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   std::vector<WinDev> wins_dv[3];
   upload_windows<T>(P, wins_dv, s);
   // the plan's own image table (f and u are set by each solve)
-  const int nred = (int)std::max<long long>(1, std::min<long long>(kRedBlocks, (N + kRedThreads - 1) / kRedThreads));
+  // blocks of the FP64 reductions: at least 8 entries per thread, since every block adds one
+  // ticket to the last-block count and those same-address atomics serialise
+  const int nred = (int)std::max<long long>(
+      1, std::min<long long>(kRedBlocks, (N + 8 * kRedThreads - 1) / (8 * kRedThreads)));
   NLD_HIP(hipHostMalloc((void**)&P.img_host, sizeof(ImgDev), hipHostMallocDefault));
   ImgDev& im = *P.img_host;
   im = ImgDev{};
