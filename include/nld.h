@@ -145,8 +145,7 @@ typedef struct {
                      /* summed once per plan on the plan's grids; Gamma_l: K_l, zero diagonal) */
   int32_t deflate;   /* 1: change of basis removing the eigenvector 1 (Sec. 4.2, 5.4)      */
   int32_t true_residual; /* 1: also compute the true residual at exit (one more matvec)     */
-  int32_t timing;    /* 1: time the first operator application of every chunk of four      */
-                     /* iterations with HIP events on the stream s                          */
+  int32_t timing;    /* 1: time every operator application with HIP events on the stream s   */
 } nld_pcg_opts;
 
 typedef struct {

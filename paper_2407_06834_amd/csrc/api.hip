@@ -136,7 +136,7 @@ nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t 
     P.oversampling = os;
     P.tol = tol;
     P.tile3 = desc->tile;
-    NLD_HIP(hipHostMalloc((void**)&P.st_host, 2 * sizeof(nld::CgState), hipHostMallocDefault));
+    NLD_HIP(hipHostMalloc((void**)&P.st_host, sizeof(nld::CgState), hipHostMallocDefault));
     int dev = 0, lds = 65536;
     NLD_HIP(hipGetDevice(&dev));
     NLD_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));

@@ -233,7 +233,7 @@ struct Plan {
   void* z = nullptr; void* r = nullptr; void* p = nullptr; void* q = nullptr;
   double* red = nullptr;           // reduction partials [kRedBlocks][8]
   CgState* st = nullptr;           // device CG state
-  CgState* st_host = nullptr;      // pinned mirrors [2] (read back alternately between chunks)
+  CgState* st_host = nullptr;      // pinned mirror
   // launch description of this plan alone, its image table and a pinned host mirror of it; the
   // fused schedule (plane kernels) and the unfused one (three convolution passes), which the
   // per-window products of the gradient use

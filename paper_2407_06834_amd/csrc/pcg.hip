@@ -266,7 +266,7 @@ nld_status run_pcg_t(Plan& P, double alpha, const void* f, void* u, const nld_pc
   const bool trace = std::getenv("NLD_TRACE_CG") != nullptr;
   const int chunk = trace ? 1 : 4;
   int launched = 0;
-  // optional event pairs around the first operator application of every chunk
+  // optional event pairs around every operator application of the loop
   std::vector<hipEvent_t> ev;
   auto new_event = [&]() {
     hipEvent_t e;
@@ -274,44 +274,25 @@ nld_status run_pcg_t(Plan& P, double alpha, const void* f, void* u, const nld_pc
     ev.push_back(e);
     return e;
   };
-  // The host reads the state back after every chunk of iterations while the next chunk is
-  // already queued, so the device never waits for the host between chunks; once the solve has
-  // finished, the kernels of the chunk in flight return at once.
-  CgState* hb[2] = {h, h + 1};
-  hipEvent_t got[2];
-  for (hipEvent_t& e : got) NLD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  auto read_state = [&](int b) {
-    NLD_HIP(hipMemcpyAsync(hb[b], P.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-    NLD_HIP(hipEventRecord(got[b], s));
-  };
-  auto launch_chunk = [&]() {
-    for (int k = 0; k < chunk && launched < o.maxit; ++k) {
-      const bool timed = o.timing && k == 0;
-      if (timed) NLD_HIP(hipEventRecord(new_event(), s));
+  while (true) {
+    NLD_HIP(hipMemcpyAsync(h, P.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    NLD_HIP(hipStreamSynchronize(s));
+    if (trace)
+      std::fprintf(stderr, "cg it=%d done=%d st=%d rr=%.6e rho=%.6e a=%.6e beta=%.6e mean_t=%.3e "
+                   "mean_q=%.3e mean_r=%.3e b2=%.6e pq=%.6e rho_new=%.6e\n", h->iters, h->done, h->status,
+                   h->rr, h->rho, h->a, h->beta, h->mean_t, h->mean_q, h->mean_r, h->bnorm2,
+                   h->last_pq, h->last_rho);
+    if (h->done || launched >= o.maxit) break;
+    for (int k = 0; k < chunk; ++k) {
+      if (o.timing) NLD_HIP(hipEventRecord(new_event(), s));
       matvec(P, nullptr, nullptr, EPI_CG_Q, s);
-      if (timed) NLD_HIP(hipEventRecord(new_event(), s));
+      if (o.timing) NLD_HIP(hipEventRecord(new_event(), s));
       hipLaunchKernelGGL(k_cg_update<T>, rb, dim3(kRedThreads), 0, s, im);
       hipLaunchKernelGGL(k_cg_direction<T>, gb, dim3(256), 0, s, im, 0);
       NLD_HIP(hipGetLastError());
       ++launched;
     }
-  };
-  int b = 0;
-  read_state(b);                          // the state after the initial residual
-  while (true) {
-    launch_chunk();                       // runs while the previous state is read
-    NLD_HIP(hipEventSynchronize(got[b]));
-    const CgState* cur = hb[b];
-    if (trace)
-      std::fprintf(stderr, "cg it=%d done=%d st=%d rr=%.6e rho=%.6e a=%.6e beta=%.6e mean_t=%.3e "
-                   "mean_q=%.3e mean_r=%.3e b2=%.6e pq=%.6e rho_new=%.6e\n", cur->iters, cur->done,
-                   cur->status, cur->rr, cur->rho, cur->a, cur->beta, cur->mean_t, cur->mean_q,
-                   cur->mean_r, cur->bnorm2, cur->last_pq, cur->last_rho);
-    if (cur->done || launched >= o.maxit) break;
-    b ^= 1;
-    read_state(b);                        // the state after the chunk just launched
   }
-  for (hipEvent_t e : got) (void)hipEventDestroy(e);
   hipLaunchKernelGGL(k_cg_finish<T>, gb, dim3(256), 0, s, im);
   NLD_HIP(hipGetLastError());
   double rr_true = -1.0;
@@ -328,8 +309,7 @@ nld_status run_pcg_t(Plan& P, double alpha, const void* f, void* u, const nld_pc
   info.matvecs_timed = 0;
   if (o.timing) {
     // operator applications after convergence return at once: count only the executed ones
-    // (the timed application of chunk j is iteration j * chunk, executed when below iters)
-    const int used = std::min<int>((int)ev.size() / 2, (h->iters + chunk - 1) / chunk);
+    const int used = std::min<int>((int)ev.size() / 2, h->iters);
     double tot = 0.0;
     for (int k = 0; k < used; ++k) {
       float ms = 0.f;
