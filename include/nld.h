@@ -115,7 +115,10 @@ nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t 
 nld_status nfft_plan_update_kernel(nfft_plan_t plan, const double* sigma, const double* weight,
                                    hipStream_t s);
 
-/* Release every device buffer of the plan (enqueued on the plan's last stream). */
+/* Release the plan.  Waits for the plan's last stream, then hands the plan's device buffers to
+ * the library's per-device cache, from which later plans take theirs (at most 8 GiB cached per
+ * device; beyond that buffers are freed).  No work using the plan may still be in flight on
+ * another stream. */
 nld_status nfft_plan_destroy(nfft_plan_t plan);
 
 /* Copy the chosen parameters of window l into *info (host). */

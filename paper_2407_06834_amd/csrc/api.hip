@@ -136,7 +136,7 @@ nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t 
     P.oversampling = os;
     P.tol = tol;
     P.tile3 = desc->tile;
-    NLD_HIP(hipHostMalloc((void**)&P.st_host, sizeof(nld::CgState), hipHostMallocDefault));
+    P.st_host = (nld::CgState*)nld::pinned_get(sizeof(nld::CgState));
     int dev = 0, lds = 65536;
     NLD_HIP(hipGetDevice(&dev));
     NLD_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -147,7 +147,7 @@ nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t 
   if (st != NLD_OK) {
     if (h) {
       nld::release_plan(h->P);
-      if (h->P.st_host) (void)hipHostFree(h->P.st_host);
+      nld::pinned_put(h->P.st_host);
       delete h;
     }
     return st;
@@ -174,7 +174,7 @@ nld_status nfft_plan_update_kernel(nfft_plan_t plan, const double* sigma, const 
 nld_status nfft_plan_destroy(nfft_plan_t plan) {
   if (!plan) return fail(NLD_E_INVAL, "nfft_plan_destroy: null plan");
   nld::release_plan(plan->P);
-  if (plan->P.st_host) (void)hipHostFree(plan->P.st_host);
+  nld::pinned_put(plan->P.st_host);
   delete plan;
   return NLD_OK;
 }

@@ -234,6 +234,7 @@ struct Plan {
   double* red = nullptr;           // reduction partials [kRedBlocks][8]
   CgState* st = nullptr;           // device CG state
   CgState* st_host = nullptr;      // pinned mirror
+  std::vector<void*> staging;      // pinned blocks of host-to-device copies in flight
   // launch description of this plan alone, its image table and a pinned host mirror of it; the
   // fused schedule (plane kernels) and the unfused one (three convolution passes), which the
   // per-window products of the gradient use
@@ -260,6 +261,10 @@ struct Plan {
 // plan construction (plan.hip)
 void build_plan(Plan& P, const void* features, hipStream_t s);
 void release_plan(Plan& P);
+// pinned host block of at least `bytes` (zeroed unless zero = false), reused across calls;
+// pinned_put returns it
+void* pinned_get(size_t bytes, bool zero = true);
+void pinned_put(void* p);
 void launch_features(const void* img, int n1, int n2, int rho, int with_pos, nld_prec prec,
                      void* F, hipStream_t s);
 // feature ranking (mis.hip)

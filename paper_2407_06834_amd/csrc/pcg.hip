@@ -453,7 +453,7 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
     if (graph) (void)hipGraphDestroy(graph);
     for (void* b : owned) (void)hipFreeAsync(b, cs);
     (void)hipStreamSynchronize(cs);
-    if (sth) (void)hipHostFree(sth);
+    pinned_put(sth);
     (void)hipEventDestroy(ev_in);
     (void)hipEventDestroy(ev_out);
   };
@@ -569,7 +569,7 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
     // ---- degree vectors (every image, if any plan still lacks its own) and max eta
     bool need_D = false;
     for (int b = 0; b < count; ++b) need_D = need_D || !plans[b]->have_D;
-    NLD_HIP(hipHostMalloc((void**)&sth, (size_t)count * sizeof(CgState), hipHostMallocDefault));
+    sth = (CgState*)pinned_get((size_t)count * sizeof(CgState));
     if (need_D) {
       matvec_set(ls, VecArg{nullptr, V_ONES}, VecArg{nullptr, V_Q}, nullptr, EPI_DEGREE, cs);
       double* d_max = nullptr;

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <stdexcept>
 
@@ -175,16 +176,107 @@ __global__ void k_scan_add(unsigned* __restrict__ data, long long n, const unsig
     if (b0 + k < n) data[b0 + k] += add;
 }
 
+// Device buffers of plans come from a per-device cache.  Plans are built and released once per
+// kernel width on the solver's path, a plan holds about 45 buffers and its build some 20
+// temporaries, and hipMallocAsync / hipFreeAsync cost tens of microseconds of host time each.
+// A released buffer enters the cache once its stream has been synchronised (dev_synced); a
+// request takes the smallest cached buffer of at least its size and at most 5/4 of it plus
+// 64 KiB.  Beyond kDevCacheCap bytes per device, released buffers are freed instead.
+namespace {
+constexpr size_t kDevCacheCap = 8ULL << 30;
+constexpr int kMaxDevices = 64;
+std::mutex g_dev_mu;
+std::multimap<size_t, void*> g_dev_free[kMaxDevices];            // bytes -> cached buffer
+std::map<void*, std::pair<int, size_t>> g_dev_owner;              // buffer -> (device, bytes)
+std::map<hipStream_t, std::vector<void*>> g_dev_pending;          // released, not yet synced
+size_t g_dev_cached[kMaxDevices] = {};
+
+int current_device() {
+  int dev = 0;
+  NLD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw std::runtime_error("device index out of range");
+  return dev;
+}
+
+void* dev_get(size_t bytes, hipStream_t s) {
+  const int dev = current_device();
+  {
+    std::lock_guard<std::mutex> lock(g_dev_mu);
+    auto& fl = g_dev_free[dev];
+    auto it = fl.lower_bound(bytes);
+    if (it != fl.end() && it->first <= bytes + bytes / 4 + (64 << 10)) {
+      void* p = it->second;
+      g_dev_cached[dev] -= it->first;
+      fl.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMallocAsync(&p, bytes, s);
+  if (e != hipSuccess) throw HipError{e, "hipMallocAsync"};
+  std::lock_guard<std::mutex> lock(g_dev_mu);
+  g_dev_owner[p] = {dev, bytes};
+  return p;
+}
+
+// p is idle (its stream has been synchronised): keep it for a later request, or free it
+void dev_release_idle(void* p) {
+  if (!p) return;
+  std::unique_lock<std::mutex> lock(g_dev_mu);
+  auto it = g_dev_owner.find(p);
+  if (it == g_dev_owner.end()) return;
+  const int dev = it->second.first;
+  const size_t bytes = it->second.second;
+  if (g_dev_cached[dev] + bytes <= kDevCacheCap) {
+    g_dev_free[dev].emplace(bytes, p);
+    g_dev_cached[dev] += bytes;
+    return;
+  }
+  g_dev_owner.erase(it);
+  lock.unlock();
+  (void)hipFree(p);
+}
+}  // namespace
+
+// the buffers released on stream s since its last synchronisation enter the cache
+void dev_synced(hipStream_t s) {
+  std::vector<void*> done;
+  {
+    std::lock_guard<std::mutex> lock(g_dev_mu);
+    auto it = g_dev_pending.find(s);
+    if (it == g_dev_pending.end()) return;
+    done.swap(it->second);
+    g_dev_pending.erase(it);
+  }
+  for (void* p : done) dev_release_idle(p);
+}
+
 template <typename P>
 P* dalloc(long long count, hipStream_t s) {
-  void* p = nullptr;
   if (count <= 0) count = 1;
-  hipError_t e = hipMallocAsync(&p, (size_t)count * sizeof(P), s);
-  if (e != hipSuccess) throw HipError{e, "hipMallocAsync"};
-  return (P*)p;
+  return (P*)dev_get((size_t)count * sizeof(P), s);
 }
+// released in stream order: reusable after the stream's next synchronisation (dev_synced)
 inline void dfree(void* p, hipStream_t s) {
-  if (p) (void)hipFreeAsync(p, s);
+  if (!p) return;
+  std::lock_guard<std::mutex> lock(g_dev_mu);
+  g_dev_pending[s].push_back(p);
+}
+
+// Host tables reach the device through pinned staging blocks: a copy from pageable memory holds
+// the host until it has finished, tens of microseconds each.  The blocks return to the pool at
+// the plan's next stream synchronisation (staging_done).
+static void upload(Plan& P, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  void* p = pinned_get(bytes, false);
+  P.staging.push_back(p);
+  std::memcpy(p, src, bytes);
+  NLD_HIP(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, s));
+}
+static void staging_done(Plan& P, hipStream_t s) {   // call only after synchronising s
+  for (void* p : P.staging) pinned_put(p);
+  P.staging.clear();
+  dev_synced(s);
 }
 
 void exclusive_scan(unsigned* data, long long n, hipStream_t s) {
@@ -478,7 +570,7 @@ static void upload_tables(Plan& P, std::vector<T>& coef_all, std::vector<T>& coe
         coef_all[((long long)l * 3 + dd) * n_max + q] = (T)P.coef_host[l][(long long)dd * n + q];
   }
   if (!P.coef) P.coef = dalloc<T>((long long)coef_all.size(), s);
-  NLD_HIP(hipMemcpyAsync(P.coef, coef_all.data(), coef_all.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  upload(P, P.coef, coef_all.data(), coef_all.size() * sizeof(T), s);
   for (int l = 0; l < L; ++l) {
     P.wins[l].coef = (const T*)P.coef + (long long)l * 3 * n_max;
     P.wins[l].n_max = n_max;
@@ -503,8 +595,7 @@ static void upload_tables(Plan& P, std::vector<T>& coef_all, std::vector<T>& coe
     }
   }
   if (!P.coef_dv) P.coef_dv = dalloc<T>((long long)coef_dv_all.size(), s);
-  NLD_HIP(hipMemcpyAsync(P.coef_dv, coef_dv_all.data(), coef_dv_all.size() * sizeof(T),
-                         hipMemcpyHostToDevice, s));
+  upload(P, P.coef_dv, coef_dv_all.data(), coef_dv_all.size() * sizeof(T), s);
 }
 
 // Device copies of the window descriptors: one with the kernel multipliers, and one per
@@ -514,13 +605,13 @@ static void upload_windows(Plan& P, std::vector<WinDev> (&wins_dv)[3], hipStream
   const int L = P.L;
   const size_t table = 3ULL * P.n_max * L;
   if (!P.d_wins) P.d_wins = dalloc<WinDev>(L, s);
-  NLD_HIP(hipMemcpyAsync(P.d_wins, P.wins.data(), L * sizeof(WinDev), hipMemcpyHostToDevice, s));
+  upload(P, P.d_wins, P.wins.data(), L * sizeof(WinDev), s);
   for (int d = 0; d < 3; ++d) {
     wins_dv[d] = P.wins;
     for (int l = 0; l < L; ++l)
       wins_dv[d][l].coef = (const T*)P.coef_dv + (size_t)d * table + (size_t)l * 3 * P.n_max;
     if (!P.d_wins_dv[d]) P.d_wins_dv[d] = dalloc<WinDev>(L, s);
-    NLD_HIP(hipMemcpyAsync(P.d_wins_dv[d], wins_dv[d].data(), L * sizeof(WinDev), hipMemcpyHostToDevice, s));
+    upload(P, P.d_wins_dv[d], wins_dv[d].data(), L * sizeof(WinDev), s);
   }
 }
 
@@ -536,13 +627,14 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   const int nblk = (int)std::min<long long>(256, (N + 255) / 256);
   int* d_cols = dalloc<int>(ncol, s);
   double* d_part = dalloc<double>(2LL * ncol * nblk, s);
-  NLD_HIP(hipMemcpyAsync(d_cols, cols.data(), ncol * sizeof(int), hipMemcpyHostToDevice, s));
+  upload(P, d_cols, cols.data(), ncol * sizeof(int), s);
   hipLaunchKernelGGL(k_minmax<T>, dim3(nblk, ncol), dim3(256), 0, s, (const T*)features, N, d_cols,
                      d_part);
   NLD_HIP(hipGetLastError());
   std::vector<double> part(2LL * ncol * nblk);
   NLD_HIP(hipMemcpyAsync(part.data(), d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   NLD_HIP(hipStreamSynchronize(s));
+  staging_done(P, s);
   dfree(d_cols, s);
   dfree(d_part, s);
   std::vector<double> lo(P.d, 0.0), hi(P.d, 0.0);
@@ -712,14 +804,14 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
       for (size_t q = 0; q < c.size(); ++q) psi_all[(size_t)l * W * (deg + 1) + q] = (T)c[q];
     }
     P.psi = dalloc<T>((long long)psi_all.size(), s);
-    NLD_HIP(hipMemcpyAsync(P.psi, psi_all.data(), psi_all.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    upload(P, P.psi, psi_all.data(), psi_all.size() * sizeof(T), s);
     for (int l = 0; l < L; ++l) P.wins[l].psi = (const T*)P.psi + (size_t)l * W * (deg + 1);
   }
 
   // ---- 3. coordinates of every (window, node)
   const long long LN = N * L;
   CoordParams* d_cp = dalloc<CoordParams>(L, s);
-  NLD_HIP(hipMemcpyAsync(d_cp, cp.data(), L * sizeof(CoordParams), hipMemcpyHostToDevice, s));
+  upload(P, d_cp, cp.data(), L * sizeof(CoordParams), s);
   unsigned* base = dalloc<unsigned>(LN, s);
   T* frac = dalloc<T>(3 * LN, s);
   unsigned* key = dalloc<unsigned>(LN, s);
@@ -748,6 +840,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   std::vector<unsigned> ht(tile_total + 1);
   NLD_HIP(hipMemcpyAsync(ht.data(), toff, (tile_total + 1) * sizeof(unsigned), hipMemcpyDeviceToHost, s));
   NLD_HIP(hipStreamSynchronize(s));
+  staging_done(P, s);
   if (ht[tile_total] != (unsigned)LN) throw std::runtime_error("internal: tile offsets do not add up");
 
   // ---- 5. schedules (host): chunks of the nodes of every non-empty tile, grouped by t;
@@ -794,12 +887,12 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   }
   P.h_tjobs = jobs;
   P.d_tjobs = dalloc<TileJob>(std::max<size_t>(1, jobs.size()), s);
-  NLD_HIP(hipMemcpyAsync(P.d_tjobs, jobs.data(), jobs.size() * sizeof(TileJob), hipMemcpyHostToDevice, s));
+  upload(P, P.d_tjobs, jobs.data(), jobs.size() * sizeof(TileJob), s);
   P.n_tiles_total = (int)tile_total;
   P.tile_slot0 = dalloc<int>(tile_total, s);
   P.tile_nslot = dalloc<int>(tile_total, s);
-  NLD_HIP(hipMemcpyAsync(P.tile_slot0, slot0.data(), tile_total * sizeof(int), hipMemcpyHostToDevice, s));
-  NLD_HIP(hipMemcpyAsync(P.tile_nslot, nslot.data(), tile_total * sizeof(int), hipMemcpyHostToDevice, s));
+  upload(P, P.tile_slot0, slot0.data(), tile_total * sizeof(int), s);
+  upload(P, P.tile_nslot, nslot.data(), tile_total * sizeof(int), s);
   P.max_padded = (int)max_padded;
   P.slot_stride = max_padded;
   P.padded = dalloc<T>((long long)std::max(1, slots) * max_padded, s);
@@ -825,7 +918,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   P.h_fjobs = fj;
   P.n_fjobs = (int)fj.size();
   P.d_fjobs = dalloc<FoldJob>(std::max<size_t>(1, fj.size()), s);
-  NLD_HIP(hipMemcpyAsync(P.d_fjobs, fj.data(), fj.size() * sizeof(FoldJob), hipMemcpyHostToDevice, s));
+  upload(P, P.d_fjobs, fj.data(), fj.size() * sizeof(FoldJob), s);
   // windows whose convolutions along the last two dimensions run fused per grid plane: FP32,
   // three kept dimensions of n = 64 or 128 points (plane, exchange buffer and twiddles in LDS)
   std::vector<char> fused(L, 0);
@@ -847,15 +940,15 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   P.pjob_begin[2] = (int)pj.size();
   P.h_pjobs = pj;
   P.d_pjobs = dalloc<PlaneJob>(std::max<size_t>(1, pj.size()), s);
-  NLD_HIP(hipMemcpyAsync(P.d_pjobs, pj.data(), pj.size() * sizeof(PlaneJob), hipMemcpyHostToDevice, s));
+  upload(P, P.d_pjobs, pj.data(), pj.size() * sizeof(PlaneJob), s);
   std::vector<Fold3Job> f3f(f3);                // the fold still runs for every window
   P.h_f3jobs = f3f;
   P.n_f3jobs = (int)f3f.size();
   P.d_f3jobs = dalloc<Fold3Job>(std::max<size_t>(1, f3f.size()), s);
-  NLD_HIP(hipMemcpyAsync(P.d_f3jobs, f3f.data(), f3f.size() * sizeof(Fold3Job), hipMemcpyHostToDevice, s));
+  upload(P, P.d_f3jobs, f3f.data(), f3f.size() * sizeof(Fold3Job), s);
   P.n_f3jobs_u = (int)f3.size();
   P.d_f3jobs_u = dalloc<Fold3Job>(std::max<size_t>(1, f3.size()), s);
-  NLD_HIP(hipMemcpyAsync(P.d_f3jobs_u, f3.data(), f3.size() * sizeof(Fold3Job), hipMemcpyHostToDevice, s));
+  upload(P, P.d_f3jobs_u, f3.data(), f3.size() * sizeof(Fold3Job), s);
 
   // convolution jobs: for each axis, lines of every window that has that axis, grouped by the
   // grid size n; each job holds the real lines one workgroup transforms (64 for n = 64 and 128,
@@ -895,13 +988,11 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     P.h_conv[ax] = cjobs_f[ax];
     if (!cjobs_f[ax].empty()) {
       P.d_conv[ax] = dalloc<ConvJob>(cjobs_f[ax].size(), s);
-      NLD_HIP(hipMemcpyAsync(P.d_conv[ax], cjobs_f[ax].data(), cjobs_f[ax].size() * sizeof(ConvJob),
-                             hipMemcpyHostToDevice, s));
+      upload(P, P.d_conv[ax], cjobs_f[ax].data(), cjobs_f[ax].size() * sizeof(ConvJob), s);
     }
     if (!cjobs_all[ax].empty()) {
       P.d_conv_u[ax] = dalloc<ConvJob>(cjobs_all[ax].size(), s);
-      NLD_HIP(hipMemcpyAsync(P.d_conv_u[ax], cjobs_all[ax].data(), cjobs_all[ax].size() * sizeof(ConvJob),
-                             hipMemcpyHostToDevice, s));
+      upload(P, P.d_conv_u[ax], cjobs_all[ax].data(), cjobs_all[ax].size() * sizeof(ConvJob), s);
     }
   }
 
@@ -949,7 +1040,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   // ticket to the last-block count and those same-address atomics serialise
   const int nred = (int)std::max<long long>(
       1, std::min<long long>(kRedBlocks, (N + 8 * kRedThreads - 1) / (8 * kRedThreads)));
-  NLD_HIP(hipHostMalloc((void**)&P.img_host, sizeof(ImgDev), hipHostMallocDefault));
+  P.img_host = (ImgDev*)pinned_get(sizeof(ImgDev));
   ImgDev& im = *P.img_host;
   im = ImgDev{};
   im.N = N;
@@ -1016,6 +1107,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   dfree(val, s);
   dfree(toff, s);
   NLD_HIP(hipStreamSynchronize(s));
+  staging_done(P, s);
   P.have_D = false;
 }
 
@@ -1035,6 +1127,45 @@ static void keep_pool_memory() {
   uint64_t keep = ~0ULL;
   NLD_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
   done[dev] = true;
+}
+
+// Small pinned host blocks (CG state mirrors, image tables) are reused across plans and solves:
+// hipHostMalloc and hipHostFree of even a few hundred bytes take on the order of a millisecond,
+// more than the rest of a plan's release.  Blocks are kept by size class (powers of two from
+// 4 KiB) for the life of the process and handed out zeroed.
+namespace {
+std::mutex g_pinned_mu;
+std::map<size_t, std::vector<void*>> g_pinned_free;     // size class -> free blocks
+std::map<void*, size_t> g_pinned_class;                 // block -> its size class
+}  // namespace
+
+void* pinned_get(size_t bytes, bool zero) {
+  size_t cls = 4096;
+  while (cls < bytes) cls <<= 1;
+  void* p = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_pinned_mu);
+    auto& fl = g_pinned_free[cls];
+    if (!fl.empty()) {
+      p = fl.back();
+      fl.pop_back();
+    }
+  }
+  if (!p) {
+    NLD_HIP(hipHostMalloc(&p, cls, hipHostMallocDefault));
+    std::lock_guard<std::mutex> lock(g_pinned_mu);
+    g_pinned_class[p] = cls;
+  }
+  if (zero) std::memset(p, 0, bytes);
+  return p;
+}
+
+void pinned_put(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lock(g_pinned_mu);
+  auto it = g_pinned_class.find(p);
+  if (it == g_pinned_class.end()) return;                // not from pinned_get: leave it alone
+  g_pinned_free[it->second].push_back(p);
 }
 
 void build_plan(Plan& P, const void* features, hipStream_t s) {
@@ -1096,6 +1227,7 @@ static void update_kernel_t(Plan& P, const double* sigma, const double* weight, 
   std::vector<WinDev> wins_dv[3];
   upload_windows<T>(P, wins_dv, s);
   NLD_HIP(hipStreamSynchronize(s));
+  staging_done(P, s);
   P.have_D = false;
   P.have_D2 = false;
   P.have_dl = false;
@@ -1126,14 +1258,14 @@ static void ensure_l2_t(Plan& P, hipStream_t s) {
     }
   }
   if (!P.coef_b) P.coef_b = dalloc<T>((long long)cb.size(), s);
-  NLD_HIP(hipMemcpyAsync(P.coef_b, cb.data(), cb.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  upload(P, P.coef_b, cb.data(), cb.size() * sizeof(T), s);
   std::vector<WinDev> wb(P.wins);
   for (int l = 0; l < L; ++l) {
     wb[l].coef = (const T*)P.coef_b + (size_t)l * 3 * n_max;
     wb[l].weight = P.weight[l] * P.weight[l];
   }
   if (!P.d_wins_b) P.d_wins_b = dalloc<WinDev>(L, s);
-  NLD_HIP(hipMemcpyAsync(P.d_wins_b, wb.data(), L * sizeof(WinDev), hipMemcpyHostToDevice, s));
+  upload(P, P.d_wins_b, wb.data(), L * sizeof(WinDev), s);
   if (!P.D2) P.D2 = dalloc<double>(P.N, s);
   LaunchSet lb = P.ls_unfused;
   lb.d_wins = P.d_wins_b;
@@ -1141,6 +1273,7 @@ static void ensure_l2_t(Plan& P, hipStream_t s) {
   P.img_host->D2 = P.D2;
   NLD_HIP(hipMemcpyAsync(P.d_img, P.img_host, sizeof(ImgDev), hipMemcpyHostToDevice, s));
   NLD_HIP(hipStreamSynchronize(s));   // host staging above is released on return
+  staging_done(P, s);
   P.have_D2 = true;
 }
 
@@ -1163,9 +1296,10 @@ void release_plan(Plan& P) {
                   P.d_wins_dv[1], P.d_wins_dv[2], P.grid_save, P.yk, P.yks, P.dl, P.dls,
                   P.adj_part, P.d_img, P.d_pjobs, P.d_f3jobs_u, P.d_conv_u[0], P.d_conv_u[1],
                   P.d_conv_u[2], P.coef_b, P.d_wins_b, P.D2};
-  for (void* b : bufs) dfree(b, s);
   (void)hipStreamSynchronize(s);
-  if (P.img_host) (void)hipHostFree(P.img_host);
+  staging_done(P, s);
+  for (void* b : bufs) dev_release_idle(b);
+  pinned_put(P.img_host);
   P.img_host = nullptr;
 }
 
