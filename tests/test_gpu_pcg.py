@@ -106,6 +106,19 @@ def test_maxit_returns_noconv_and_last_iterate():
     assert abs(float(u.mean()) - f.mean()) < 1e-12
 
 
+def test_timing_counts_the_executed_products():
+    # the event-timed products are the executed loop iterations (launches after convergence
+    # return at once and are not counted)
+    torch, nld, f, img, F, wins, wts, plan = _problem(32, 32, 1, 5, torch_gpu().float32,
+                                                      [0.1] * 4, 32, 4)
+    u, info = plan.pcg_solve(5.0, img.reshape(-1), tol=1e-6, maxit=200, timing=True)
+    plan.close()
+    it = info["iters"]
+    assert info["status"] == "OK" and it > 0
+    assert info["matvecs_timed"] == it
+    assert 0.0 < info["ms_matvec"] < 100.0
+
+
 def test_warm_start_from_solution_converges_immediately():
     torch, nld, f, img, F, wins, wts, plan = _problem(32, 32, 1, 6, torch_gpu().float64,
                                                       [0.1] * 4, 32, 6)
