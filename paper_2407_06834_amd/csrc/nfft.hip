@@ -1032,7 +1032,12 @@ template <typename T, int W, int TD, int TSC>
 __global__ void __launch_bounds__(kGatherThreads)
 k_gather(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int job0,
          const ImgDev* __restrict__ imgs, int check, int stage_min) {
-  const TileJob job = jobs[job0 + blockIdx.x];
+  // Workgroups are dealt round-robin to the 8 XCDs in launch order.  XCD x takes the x-th of
+  // eight contiguous ranges of the jobs (tile order between ranges, largest chunks first within
+  // one), so neighbouring tiles, whose padded tiles share grid cells, are staged through one L2.
+  const int nj = gridDim.x, x = blockIdx.x % 8, k = blockIdx.x / 8;
+  const int jx = x * (nj / 8) + min(x, nj % 8) + k;
+  const TileJob job = jobs[job0 + jx];
   const WinDev& w = wins[job.win];
   if (check && imgs[w.img].st->done) return;
   extern __shared__ unsigned char smem_raw[];
@@ -1265,8 +1270,9 @@ void launch_tiles(const LaunchSet& ls, VecArg in, int check, hipStream_t s, bool
       auto k = (g == 0) ? k_gather<T, W, 1, 0> : (g == 1) ? k_gather<T, W, 2, 0>
              : c8 ? k_gather<T, W, 3, 8> : k_gather<T, W, 3, 0>;
       allow_lds(k, lds);
-      hipLaunchKernelGGL(k, dim3(nj), dim3(kGatherThreads), lds, s, ls.d_wins, ls.d_tjobs, j0,
-                         ls.d_imgs, check, gather_stage_min());
+      hipLaunchKernelGGL(k, dim3(nj), dim3(kGatherThreads), lds, s, ls.d_wins,
+                         ls.d_gjobs ? ls.d_gjobs : ls.d_tjobs, j0, ls.d_imgs, check,
+                         gather_stage_min());
     }
     NLD_HIP(hipGetLastError());
   }

@@ -134,6 +134,7 @@ struct LaunchSet {
   int m = 4;                                    // cutoff (equal for every window of the set)
   const WinDev* d_wins = nullptr;
   const TileJob* d_tjobs = nullptr;
+  const TileJob* d_gjobs = nullptr;             // the gathering's order of the same jobs
   int tjob_begin[4] = {0, 0, 0, 0};             // group g: windows with t = g + 1
   int max_padded = 1;                           // largest padded tile (cells)
   int ts3 = 0;                                  // 8 if every 3-D window has 8^3 tiles, else 0
@@ -244,6 +245,8 @@ struct Plan {
   ImgDev* img_host = nullptr;
   // host copies of the schedules (a batch concatenates them)
   std::vector<TileJob> h_tjobs;
+  std::vector<TileJob> h_gjobs;                  // tile order, same groups (gathering)
+  TileJob* d_gjobs = nullptr;
   std::vector<Fold3Job> h_f3jobs;
   std::vector<FoldJob> h_fjobs;
   std::vector<ConvJob> h_conv[3];
@@ -261,6 +264,9 @@ struct Plan {
 // plan construction (plan.hip)
 void build_plan(Plan& P, const void* features, hipStream_t s);
 void release_plan(Plan& P);
+// the gathering's order of the tile-ordered jobs [begin, end): eight contiguous ranges, one per
+// XCD, each with its largest chunks first
+void gather_order(std::vector<TileJob>& jobs, size_t begin, size_t end);
 // pinned host block of at least `bytes` (zeroed unless zero = false), reused across calls;
 // pinned_put returns it
 void* pinned_get(size_t bytes, bool zero = true);

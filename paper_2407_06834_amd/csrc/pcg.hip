@@ -460,7 +460,7 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
   try {
     // ---- concatenated tables
     std::vector<WinDev> wins;
-    std::vector<TileJob> tj[3];
+    std::vector<TileJob> tj[3], gj[3];
     std::vector<Fold3Job> f3[2];
     std::vector<FoldJob> fj;
     std::vector<ConvJob> cj[3][4];
@@ -491,6 +491,9 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
           TileJob t = P.h_tjobs[j];
           t.win += wo;
           tj[g].push_back(t);
+          TileJob u = P.h_gjobs[j];
+          u.win += wo;
+          gj[g].push_back(u);
         }
       for (Fold3Job j : P.h_f3jobs) {
         j.win += wo;
@@ -527,14 +530,16 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
       ls.max_nred = std::max(ls.max_nred, im.nred);
       ls.has_flat = ls.has_flat || P.has_flat;
     }
-    std::vector<TileJob> tjobs;
+    std::vector<TileJob> tjobs, gjobs;
     for (int g = 0; g < 3; ++g) {
-      // largest chunks first, across the whole batch
+      // largest chunks first, across the whole batch; the gathering's order per XCD range
       std::stable_sort(tj[g].begin(), tj[g].end(), [](const TileJob& a, const TileJob& b) {
         return (a.pend - a.pbeg) > (b.pend - b.pbeg);
       });
       ls.tjob_begin[g] = (int)tjobs.size();
       tjobs.insert(tjobs.end(), tj[g].begin(), tj[g].end());
+      gjobs.insert(gjobs.end(), gj[g].begin(), gj[g].end());
+      gather_order(gjobs, ls.tjob_begin[g], gjobs.size());
     }
     ls.tjob_begin[3] = (int)tjobs.size();
     std::vector<Fold3Job> f3all(f3[0]);
@@ -545,6 +550,7 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
     ls.n_fjobs = (int)fj.size();
     ls.d_wins = dev_copy(wins, cs, owned);
     ls.d_tjobs = dev_copy(tjobs, cs, owned);
+    ls.d_gjobs = dev_copy(gjobs, cs, owned);
     ls.d_f3jobs = dev_copy(f3all, cs, owned);
     ls.d_fjobs = dev_copy(fj, cs, owned);
     for (int ax = 0; ax < 3; ++ax) {

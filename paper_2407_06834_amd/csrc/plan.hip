@@ -868,6 +868,15 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     }
   }
   P.tjob_begin[3] = (int)jobs.size();
+  // the gathering: tile order (neighbouring tiles stage overlapping grid cells), largest chunks
+  // first within each XCD's range
+  P.h_gjobs = jobs;
+  {
+    std::vector<TileJob> gj(jobs);
+    for (int g = 0; g < 3; ++g) gather_order(gj, P.tjob_begin[g], P.tjob_begin[g + 1]);
+    P.d_gjobs = dalloc<TileJob>(std::max<size_t>(1, gj.size()), s);
+    upload(P, P.d_gjobs, gj.data(), gj.size() * sizeof(TileJob), s);
+  }
   // largest chunks first within each group, so the long workgroups start early
   for (int g = 0; g < 3; ++g)
     std::stable_sort(jobs.begin() + P.tjob_begin[g], jobs.begin() + P.tjob_begin[g + 1],
@@ -1067,6 +1076,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   ls.m = P.wins[0].m;
   ls.d_wins = P.d_wins;
   ls.d_tjobs = P.d_tjobs;
+  ls.d_gjobs = P.d_gjobs;
   for (int g = 0; g < 4; ++g) ls.tjob_begin[g] = P.tjob_begin[g];
   ls.max_padded = P.max_padded;
   ls.ts3 = (P.f3_ts == 8) ? 8 : 0;
@@ -1166,6 +1176,17 @@ void pinned_put(void* p) {
   auto it = g_pinned_class.find(p);
   if (it == g_pinned_class.end()) return;                // not from pinned_get: leave it alone
   g_pinned_free[it->second].push_back(p);
+}
+
+void gather_order(std::vector<TileJob>& jobs, size_t begin, size_t end) {
+  const size_t nj = end - begin;
+  for (size_t x = 0; x < 8; ++x) {
+    const size_t b = begin + x * (nj / 8) + std::min(x, nj % 8);
+    const size_t e = b + nj / 8 + (x < nj % 8 ? 1 : 0);
+    std::stable_sort(jobs.begin() + b, jobs.begin() + e, [](const TileJob& p, const TileJob& q) {
+      return (p.pend - p.pbeg) > (q.pend - q.pbeg);
+    });
+  }
 }
 
 void build_plan(Plan& P, const void* features, hipStream_t s) {
@@ -1291,7 +1312,7 @@ void update_kernel(Plan& P, const double* sigma, const double* weight, hipStream
 void release_plan(Plan& P) {
   hipStream_t s = P.stream;
   void* bufs[] = {P.d_wins, P.g_idx, P.g_base, P.g_frac, P.coef, P.grid, P.padded, P.tile_slot0,
-                  P.tile_nslot, P.ylocal, P.D, P.sumv, P.ones, P.psi, P.d_tjobs, P.d_fjobs, P.d_f3jobs, P.d_conv[0], P.d_conv[1],
+                  P.tile_nslot, P.ylocal, P.D, P.sumv, P.ones, P.psi, P.d_tjobs, P.d_gjobs, P.d_fjobs, P.d_f3jobs, P.d_conv[0], P.d_conv[1],
                   P.d_conv[2], P.z, P.r, P.p, P.q, P.red, P.st, P.coef_dv, P.d_wins_dv[0],
                   P.d_wins_dv[1], P.d_wins_dv[2], P.grid_save, P.yk, P.yks, P.dl, P.dls,
                   P.adj_part, P.d_img, P.d_pjobs, P.d_f3jobs_u, P.d_conv_u[0], P.d_conv_u[1],
