@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes of one FP32 Laplacian product on this workload, from the rocprofv3 counter runs kept
 # in profiles/nfft_laplacian_512_fp32_hbm_traffic.md, valid for the kernel sources of that hash
-TRAFFIC = {"sha1": "187067b4370c0df65aba281f6d6aafb90690f74d", "bytes": 1094076970}
+TRAFFIC = {"sha1": "6418c9213667ee5024d0887cd5988a2525a911c2", "bytes": 834913906}
 KERNEL_SOURCES = ("paper_2407_06834_amd/csrc/nfft.hip", "paper_2407_06834_amd/csrc/plan.hip",
                   "paper_2407_06834_amd/csrc/nld_internal.h", "paper_2407_06834_amd/csrc/nld_device.h")
 
