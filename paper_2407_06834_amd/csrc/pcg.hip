@@ -149,17 +149,35 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_update(const ImgDev* __restr
   const long long N = im.N;
   const double a = st->a, mq = st->mean_q;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < N;
-       i += (long long)im.nred * kRedThreads) {
-    z[i] = (T)((double)z[i] + a * (double)p[i]);
-    const T rt = (T)((double)r[i] - a * ((double)q[i] - mq));
-    r[i] = rt;
-    const double rv = (double)rt;
-    const double t = rv * pinv<T>(st, im, i);
-    s[0] += rv * rv;
-    s[1] += t;
-    s[2] += rv * t;
-    s[3] += rv;
+  // a thread's entries i, i + S, i + 2S, ... in that order (the sums' order); the loads of four
+  // of them are issued before any of their stores, one memory round trip per four entries
+  constexpr int U = 4;
+  const long long S = (long long)im.nred * kRedThreads;
+  for (long long i0 = blockIdx.x * (long long)kRedThreads + threadIdx.x; i0 < N; i0 += U * S) {
+    double zv[U], pv[U], rv0[U], qv[U], pi[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = i0 + u * S < N ? i0 + u * S : i0;     // past the end: a valid entry
+      zv[u] = (double)z[i];
+      pv[u] = (double)p[i];
+      rv0[u] = (double)r[i];
+      qv[u] = (double)q[i];
+      pi[u] = pinv<T>(st, im, i);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = i0 + u * S;
+      if (i >= N) break;
+      z[i] = (T)(zv[u] + a * pv[u]);
+      const T rt = (T)(rv0[u] - a * (qv[u] - mq));
+      r[i] = rt;
+      const double rv = (double)rt;
+      const double t = rv * pi[u];
+      s[0] += rv * rv;
+      s[1] += t;
+      s[2] += rv * t;
+      s[3] += rv;
+    }
   }
   double tot[4];
   if (!grid_reduce<4>(s, im.red, &st->ticket[3], tot, im.nred)) return;
