@@ -72,7 +72,7 @@ def main():
     ap.add_argument("--profile-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "independent solves would shard across GPUs with no communication, but no "
               "multi-GPU path is built or measured here.", file=sys.stderr)
         sys.exit(2)
