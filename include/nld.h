@@ -141,7 +141,11 @@ nld_status laplacian_matvec(nfft_plan_t plan, const void* v, void* y, hipStream_
 typedef struct {
   double tol;        /* stop when ||r_k||_2 <= tol * ||f - mean(f)||_2 (recursive residual) */
   int32_t maxit;     /* maximum number of iterations (operator applications)              */
-  int32_t use_u0;    /* 1: u holds the initial guess on entry; 0: start from f (Sec. 5.3)  */
+  int32_t use_u0;    /* 0: start from f (Sec. 5.3).  1: u holds an initial guess u0 on     */
+                     /* entry; a u0 whose initial residual is not finite is replaced by f.  */
+                     /* 2: as 1, and u0 is also replaced by f when its initial residual     */
+                     /* ||Pi (f - A u0)|| exceeds that of u0 = f (costs one more operator   */
+                     /* application).  Plain PCG from f is the fallback of a warm start.     */
   int32_t precond;   /* 0: none; 1: Jacobi P_a = I + alpha diag(eta); 2: the l2 diagonal   */
                      /* P_b' = (alpha^2 sum_l w_l^2 diag(Gamma_l o Gamma_l 1) + P_a^2)^(1/2) */
                      /* of Sec. 4.3.1 (squared kernels = Gaussians of width sigma_l / sqrt 2, */
@@ -160,6 +164,7 @@ typedef struct {
   double ms_matvec;     /* mean duration of one operator application (if timing), ms         */
   int32_t matvecs_timed;/* operator applications that entered the mean                       */
   nld_status status;
+  int32_t u0_rejected;  /* 1 if the initial guess was replaced by f (use_u0 = 1 or 2)        */
 } nld_pcg_info;
 
 /* Solve (I + alpha L~) u = f with deflated Jacobi PCG (Sec. 4.3.2, 5.4), projector form:
@@ -171,7 +176,9 @@ nld_status pcg_solve(nfft_plan_t plan, double alpha, const void* f, void* u,
 
 /* Independent solves of `count` plans (distinct handles, equal precision and cutoff), each
  * (I + alpha[b] L~_b) u_b = f_b with the deflated Jacobi PCG of pcg_solve and the same opts;
- * f[b] and u[b] are device vectors of plan b's N and precision (u[b] holds u0 if use_u0).
+ * f[b] and u[b] are device vectors of plan b's N and precision (u[b] holds u0 if use_u0, which
+ * must be 0 or 1 here; a non-finite u0 ends that solve with NLD_E_BREAKDOWN instead of the
+ * fallback of pcg_solve).
  * All solves advance together: every stage of an iteration is one launch over all plans, a
  * chunk of iterations is captured once as a HIP graph and replayed until every solve has
  * finished, and solves that finish early stop costing work.  Each solve's iterates are

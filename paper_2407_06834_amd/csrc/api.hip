@@ -241,8 +241,8 @@ nld_status pcg_solve(nfft_plan_t plan, double alpha, const void* f, void* u,
   if (opts->maxit < 0) return fail(NLD_E_INVAL, "pcg_solve: maxit must be >= 0");
   if (opts->precond < 0 || opts->precond > 2)
     return fail(NLD_E_INVAL, "pcg_solve: precond must be 0, 1 or 2");
-  if ((opts->deflate != 0 && opts->deflate != 1) || (opts->use_u0 != 0 && opts->use_u0 != 1))
-    return fail(NLD_E_INVAL, "pcg_solve: deflate and use_u0 must be 0 or 1");
+  if (opts->deflate != 0 && opts->deflate != 1) return fail(NLD_E_INVAL, "pcg_solve: deflate must be 0 or 1");
+  if (opts->use_u0 < 0 || opts->use_u0 > 2) return fail(NLD_E_INVAL, "pcg_solve: use_u0 must be 0, 1 or 2");
   std::memset(info, 0, sizeof(*info));
   info->relres_true = -1.0;
   nld_status result = NLD_OK;
@@ -314,8 +314,8 @@ nld_status adjoint_solve(nfft_plan_t plan, double alpha, const void* f, const vo
   if (opts->maxit < 0) return fail(NLD_E_INVAL, "adjoint_solve: maxit must be >= 0");
   if (opts->precond < 0 || opts->precond > 2)
     return fail(NLD_E_INVAL, "adjoint_solve: precond must be 0, 1 or 2");
-  if ((opts->deflate != 0 && opts->deflate != 1) || (opts->use_u0 != 0 && opts->use_u0 != 1))
-    return fail(NLD_E_INVAL, "adjoint_solve: deflate and use_u0 must be 0 or 1");
+  if (opts->deflate != 0 && opts->deflate != 1) return fail(NLD_E_INVAL, "adjoint_solve: deflate must be 0 or 1");
+  if (opts->use_u0 < 0 || opts->use_u0 > 2) return fail(NLD_E_INVAL, "adjoint_solve: use_u0 must be 0, 1 or 2");
   std::memset(info, 0, sizeof(*info));
   info->relres_true = -1.0;
   nld_status result = NLD_OK;

@@ -267,6 +267,9 @@ void release_plan(Plan& P);
 // the gathering's order of the tile-ordered jobs [begin, end): eight contiguous ranges, one per
 // XCD, each with its largest chunks first
 void gather_order(std::vector<TileJob>& jobs, size_t begin, size_t end);
+// device buffer of at least `bytes` from the library's per-device cache; a plan that stores it
+// in one of its buffer fields returns it to the cache on release
+void* plan_buffer(size_t bytes, hipStream_t s);
 // pinned host block of at least `bytes` (zeroed unless zero = false), reused across calls;
 // pinned_put returns it
 void* pinned_get(size_t bytes, bool zero = true);

@@ -84,6 +84,14 @@ __global__ void k_cg_z0(const ImgDev* __restrict__ imgs, int u0sel) {
 __device__ __forceinline__ void finish_residual(CgState* st, const double (&tot)[4], long long N,
                                                 bool count_iteration) {
   if (count_iteration) st->iters += 1;
+  // a non-finite sum (e.g. from a non-finite initial guess) is a breakdown; tested first, since
+  // the clamp below would turn a NaN residual into 0
+  if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(tot[2]) || !isfinite(tot[3])) {
+    st->rr = tot[0];
+    st->done = 1;
+    st->status = NLD_E_BREAKDOWN;
+    return;
+  }
   const double dN = (double)N;
   const double c = st->deflate ? tot[3] / dN : 0.0;
   const double rr = fmax(tot[0] - c * c * dN, 0.0);
@@ -270,15 +278,53 @@ nld_status run_pcg_t(Plan& P, double alpha, const void* f, void* u, const nld_pc
   P.img_host->vec[V_F] = const_cast<void*>(f);
   P.img_host->vec[V_U] = u;
   NLD_HIP(hipMemcpyAsync(P.d_img, P.img_host, sizeof(ImgDev), hipMemcpyHostToDevice, s));
-  const int u0sel = o.use_u0 ? V_U : V_F;
   const dim3 rb(P.ls.max_nred, 1);
   const dim3 gb(grid_for(N), 1);
   const ImgDev* im = P.d_img;
-  hipLaunchKernelGGL(k_cg_stats<T>, rb, dim3(kRedThreads), 0, s, im, u0sel);
-  hipLaunchKernelGGL(k_cg_z0<T>, gb, dim3(256), 0, s, im, u0sel);
-  NLD_HIP(hipGetLastError());
-  matvec(P, nullptr, nullptr, EPI_CG_INIT, s);
-  hipLaunchKernelGGL(k_cg_init2<T>, rb, dim3(kRedThreads), 0, s, im);
+  const CgState fresh = *h;
+  // initial state and residual r0 = Pi (f_perp - A z0) of the start u0 = vec[sel]
+  auto init_from = [&](int sel, bool reset) {
+    if (reset) {
+      *h = fresh;
+      NLD_HIP(hipMemcpyAsync(P.st, h, sizeof(CgState), hipMemcpyHostToDevice, s));
+    }
+    hipLaunchKernelGGL(k_cg_stats<T>, rb, dim3(kRedThreads), 0, s, im, sel);
+    hipLaunchKernelGGL(k_cg_z0<T>, gb, dim3(256), 0, s, im, sel);
+    NLD_HIP(hipGetLastError());
+    matvec(P, nullptr, nullptr, EPI_CG_INIT, s);
+    hipLaunchKernelGGL(k_cg_init2<T>, rb, dim3(kRedThreads), 0, s, im);
+    NLD_HIP(hipGetLastError());
+  };
+  auto read_state = [&]() {
+    NLD_HIP(hipMemcpyAsync(h, P.st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    NLD_HIP(hipStreamSynchronize(s));
+  };
+  info.u0_rejected = 0;
+  if (!o.use_u0) {
+    init_from(V_F, false);
+  } else {
+    // warm start with plain PCG as the fallback: a guess whose initial residual is not finite
+    // (use_u0 = 1), or also exceeds the residual of the plain start u0 = f (use_u0 = 2), is
+    // replaced by f
+    double rr_f = INFINITY;
+    bool plain_done = false;
+    if (o.use_u0 == 2) {
+      init_from(V_F, false);
+      read_state();
+      rr_f = h->rr;
+      plain_done = h->done != 0;          // constant f, or f already within the tolerance
+    }
+    if (!plain_done) {
+      init_from(V_U, o.use_u0 == 2);
+      read_state();
+      const bool bad = h->status == NLD_E_BREAKDOWN || !std::isfinite(h->rr) ||
+                       (o.use_u0 == 2 && h->rr > rr_f);
+      if (bad) {
+        info.u0_rejected = 1;
+        init_from(V_F, true);
+      }
+    }
+  }
   hipLaunchKernelGGL(k_cg_direction<T>, gb, dim3(256), 0, s, im, 1);
   NLD_HIP(hipGetLastError());
   const bool trace = std::getenv("NLD_TRACE_CG") != nullptr;
@@ -370,8 +416,8 @@ nld_status run_adjoint(Plan& P, double alpha, const void* u, const void* g, void
   // adjoint state: A p = g with the same symmetric operator
   const nld_status st = run_pcg(P, alpha, g, p, o, info, s);
   const long long LN = (long long)P.N * P.L;
-  auto alloc = [&](void** b, size_t bytes) {
-    if (!*b) NLD_HIP(hipMallocAsync(b, bytes, s));
+  auto alloc = [&](void** b, size_t bytes) {   // owned by the plan, returned on release
+    if (!*b) *b = plan_buffer(bytes, s);
   };
   alloc(&P.yk, LN * P.elem);
   alloc(&P.yks, LN * P.elem);

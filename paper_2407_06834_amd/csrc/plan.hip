@@ -495,6 +495,8 @@ double dim_error(double sigma, double R, int M) {
 
 }  // namespace
 
+void* plan_buffer(size_t bytes, hipStream_t s) { return dev_get(std::max<size_t>(1, bytes), s); }
+
 void launch_features(const void* img, int n1, int n2, int rho, int with_pos, nld_prec prec,
                      void* F, hipStream_t s) {
   const long long total = (long long)n1 * n2 * ((with_pos ? 2 : 0) + (2 * rho + 1) * (2 * rho + 1));

@@ -55,14 +55,16 @@ class PcgInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("relres_rec", ctypes.c_double),
                 ("relres_true", ctypes.c_double), ("kappa_est", ctypes.c_double),
                 ("ms_solve", ctypes.c_double), ("ms_matvec", ctypes.c_double),
-                ("matvecs_timed", ctypes.c_int32), ("status", ctypes.c_int32)]
+                ("matvecs_timed", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("u0_rejected", ctypes.c_int32)]
 
     def as_dict(self):
         return {"iters": self.iters, "relres_rec": self.relres_rec,
                 "relres_true": self.relres_true, "kappa_est": self.kappa_est,
                 "ms_solve": self.ms_solve, "ms_matvec": self.ms_matvec,
                 "matvecs_timed": self.matvecs_timed,
-                "status": STATUS_NAMES.get(self.status, self.status)}
+                "status": STATUS_NAMES.get(self.status, self.status),
+                "u0_rejected": bool(self.u0_rejected)}
 
 
 _lib = None
@@ -246,12 +248,16 @@ class Plan:
     def pcg_solve(self, alpha: float, f: torch.Tensor, u0: torch.Tensor | None = None,
                   tol: float = 1e-6, maxit: int = 500, precond: bool = True,
                   deflate: bool = True, true_residual: bool = False, out=None, stream=None,
-                  raise_on_noconv: bool = False, timing: bool = False):
-        """Solve (I + alpha L~) u = f.  Returns (u, info dict)."""
+                  raise_on_noconv: bool = False, timing: bool = False,
+                  u0_guard: str = "finite"):
+        """Solve (I + alpha L~) u = f.  Returns (u, info dict).  With a warm start u0,
+        u0_guard "finite" falls back to u0 = f when u0's initial residual is not finite,
+        "residual" also when it exceeds the residual of u0 = f (one more product)."""
         u = torch.empty_like(f) if out is None else out
         if u0 is not None:
             u.copy_(u0)
-        opts = PcgOpts(float(tol), int(maxit), 1 if u0 is not None else 0, _precond(precond),
+        mode = 0 if u0 is None else {"finite": 1, "residual": 2}[u0_guard]
+        opts = PcgOpts(float(tol), int(maxit), mode, _precond(precond),
                        int(bool(deflate)), int(bool(true_residual)), int(bool(timing)))
         info = PcgInfo()
         st = load().pcg_solve(self.handle, float(alpha), _vec(f, self.N, self.dtype, "f"),

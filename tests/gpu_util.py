@@ -11,6 +11,16 @@ def torch_gpu():
 
 
 def rel(a, b):
+    """Relative L2 error ||a - b|| / ||b||."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def max_rel(a, b):
+    """Largest entrywise error relative to the largest entry: max |a - b| / max |b|.  Beside the
+    relative L2 error it bounds every single entry, so a few bad entries cannot hide in the
+    norm."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))

@@ -139,3 +139,32 @@ def test_adjoint_after_kernel_update_matches_fresh_plan():
     fresh.close()
     # the two plans scale the nodes differently, so they agree to the summation accuracy
     assert np.abs(g_upd - g_new).max() < 1e-5 * np.abs(g_new).max()
+
+
+def test_repeated_plans_with_adjoint_solves_hold_no_device_memory():
+    # every buffer of a plan, the adjoint's included, returns to the library's cache on close:
+    # after the first rounds fill the cache, further rounds take no new device memory
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    _, f = make_image(41, 24, 24, 3, 2, 0.1)
+    img = torch.tensor(f, dtype=torch.float64, device="cuda")
+    F = nld.features_from_image(img, 1)
+    wins = nld.window_table(1)
+    fv = img.reshape(-1)
+
+    def round_trip():
+        plan = nld.Plan(F, wins, [0.15] * 4, [1.0] * 4, bandwidth=32, cutoff=6)
+        u, _ = plan.pcg_solve(1.0, fv, tol=1e-10)
+        plan.adjoint_solve(1.0, fv, u, (u - fv).contiguous(), tol=1e-10)
+        plan.close()
+        torch.cuda.synchronize()
+
+    for _ in range(2):
+        round_trip()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(5):
+        round_trip()
+    free1 = torch.cuda.mem_get_info()[0]
+    # one window grid set alone is 4 * 64^3 * 8 bytes = 8 MiB: a leak of the adjoint buffers
+    # would take more than 5 * 3 * 8 MiB
+    assert free0 - free1 < 16 * 2 ** 20, (free0, free1)

@@ -1,11 +1,15 @@
-"""GPU tests of the batched solves: every solve of a batch equals the solve of its plan alone,
-bit for bit, with and without the captured iteration graph."""
+"""GPU tests of the batched solves: every solve of a batch matches the oracle's dense Cholesky
+solve of its exact-kernel system, and equals the solve of its plan alone bit for bit, with and
+without the captured iteration graph."""
 import os
 
 import numpy as np
 import pytest
 
-from gpu_util import torch_gpu
+from gpu_util import max_rel, rel, torch_gpu
+from oracle import kernel as K
+from oracle import solve as OS
+from oracle.features import features_from_image as o_features
 from paper_2407_06834_amd.synth import make_image
 
 pytestmark = pytest.mark.gpu
@@ -26,6 +30,51 @@ def _problems(torch, nld, dtype, sizes=SIZES, seed=300):
         plan = nld.Plan(F, nld.window_table(1), sig, [1.0] * 4, bandwidth=64, cutoff=m)
         out.append((plan, alpha, img.reshape(-1).contiguous()))
     return out
+
+
+@pytest.mark.parametrize("dtype_name", ["float64", "float32"])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batched_solves_match_oracle_dense_solves(dtype_name, graph):
+    """Uneven sides, widths and alphas in one batch; every solution against the dense Cholesky
+    solve of the exact kernel (paper Sec. 5.3's direct solver): FP64 within 1e-6 relative L2 at
+    tolerance 1e-10 (bandwidth chosen for a 1e-10 product), FP32 within 1e-4."""
+    torch = torch_gpu()
+    from paper_2407_06834_amd import nld
+    fp64 = dtype_name == "float64"
+    dtype = getattr(torch, dtype_name)
+    rng = np.random.default_rng(350)
+    sizes = [(32, 32), (48, 40), (17, 23), (64, 56), (40, 64)]
+    plans, alphas, fs, probs = [], [], [], []
+    for k, (n1, n2) in enumerate(sizes):
+        _, f = make_image(350 + k, n1, n2, 3, 2, 0.1)
+        img = torch.tensor(f, dtype=dtype, device="cuda")
+        F = nld.features_from_image(img, 1)
+        sig = [float(x) for x in rng.uniform(0.08, 0.2, 4)]
+        alpha = float(np.exp(rng.uniform(np.log(0.05), np.log(20.0))))
+        plans.append(nld.Plan(F, nld.window_table(1), sig, [1.0] * 4, cutoff=8 if fp64 else 4,
+                              matvec_tol=1e-10 if fp64 else 1e-5))
+        alphas.append(alpha)
+        fs.append(img.reshape(-1).contiguous())
+        probs.append((f, sig, alpha))
+    if not graph:
+        os.environ["NLD_NO_GRAPH"] = "1"
+    try:
+        us, infos, st = nld.pcg_solve_batched(plans, alphas, fs, tol=1e-10 if fp64 else 1e-6,
+                                              maxit=1000)
+    finally:
+        os.environ.pop("NLD_NO_GRAPH", None)
+    for p in plans:
+        p.close()
+    assert st == nld.NLD_OK
+    for (f, sig, alpha), u, info in zip(probs, us, infos):
+        assert info["status"] == "OK"
+        W = K.anova_dense(o_features(f, 1), nld.window_table(1), sig, [1.0] * 4)
+        us_o = OS.dense_solve(K.system_dense(W, alpha), f.reshape(-1))
+        got = u.double().cpu().numpy()
+        if fp64:
+            assert rel(got, us_o) < 1e-6 and max_rel(got, us_o) < 1e-5, (f.shape, alpha, sig)
+        else:
+            assert rel(got, us_o) < 1e-4 and max_rel(got, us_o) < 1e-3, (f.shape, alpha, sig)
 
 
 @pytest.mark.parametrize("dtype_name", ["float64", "float32"])
@@ -100,3 +149,14 @@ def test_autotuner_picks_meet_the_error_target():
         assert len(chosen) == 1 and chosen[0].err <= tuner.matvec_tol
         # the highest cutoff is far more accurate than the target (sanity of the measurement)
         assert min(c.err for c in tuner.results[key] if c.cutoff == 5) < 1e-5
+        # the chosen candidate against the oracle's exact direct sums (all rows of these sizes)
+        from paper_2407_06834_amd import nld
+        img, sig, wts = samples[key]
+        F = nld.features_from_image(img, 1)
+        plan = nld.Plan(F, nld.window_table(1), sig, wts, **kw)
+        v = np.random.default_rng(7).standard_normal(F.shape[1])
+        y = plan.anova_matvec(torch.tensor(v, dtype=torch.float32, device="cuda")).cpu().numpy()
+        plan.close()
+        ref = K.anova_matvec_direct(F.double().cpu().numpy(), nld.window_table(1), sig, wts,
+                                    v.astype(np.float32).astype(np.float64))
+        assert rel(y, ref) < tuner.matvec_tol and max_rel(y, ref) < 4 * tuner.matvec_tol, key

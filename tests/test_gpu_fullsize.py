@@ -5,7 +5,7 @@ a time); the FP64 solve is checked through sampled rows of its true residual."""
 import numpy as np
 import pytest
 
-from gpu_util import rel, torch_gpu
+from gpu_util import max_rel, rel, torch_gpu
 from oracle import csum
 from paper_2407_06834_amd.synth import make_image, random_vector
 
@@ -71,6 +71,7 @@ def test_bench_product_on_sampled_rows(sigma):
         # Gaussian's Fourier series at M = 64 dominates (about 4e-4) and the bound applies
         tol = max(1e-6 if fp64 else 1e-4, 4.0 * bound)
         assert err < tol, (err, bound)
+        assert max_rel(y[rows], ref) < 4.0 * tol, (max_rel(y[rows], ref), bound)
         out[fp64] = y[rows]
     # both precisions make the same approximation: FP32 arithmetic adds at most 1e-4
     assert rel(out[False], out[True]) < 1e-4

@@ -167,3 +167,39 @@ def test_l2_preconditioned_iterations_match_oracle():
         assert info["status"] == "OK"
         assert abs(info["iters"] - it_o) <= 1, (deflate, info["iters"], it_o)
     plan.close()
+
+
+@pytest.mark.parametrize("guard", ["finite", "residual"])
+def test_non_finite_warm_start_falls_back_to_plain_pcg(guard):
+    # a guess with a NaN entry: the solve restarts from u0 = f and reproduces the plain solve
+    torch, nld, f, img, F, wins, wts, plan = _problem(32, 32, 1, 7, torch_gpu().float64,
+                                                      [0.1] * 4, 64, 6)
+    fv = img.reshape(-1)
+    u_plain, i_plain = plan.pcg_solve(1.0, fv, tol=1e-10)
+    bad = fv.clone()
+    bad[17] = float("nan")
+    u, info = plan.pcg_solve(1.0, fv, u0=bad, tol=1e-10, u0_guard=guard)
+    plan.close()
+    assert info["status"] == "OK" and info["u0_rejected"]
+    assert info["iters"] == i_plain["iters"]
+    assert torch.equal(u, u_plain)
+
+
+def test_worse_warm_start_falls_back_only_with_the_residual_guard():
+    # a finite guess far worse than f: kept by the finite guard, replaced by the residual guard
+    torch, nld, f, img, F, wins, wts, plan = _problem(32, 32, 1, 8, torch_gpu().float64,
+                                                      [0.1] * 4, 64, 6)
+    fv = img.reshape(-1)
+    u_plain, i_plain = plan.pcg_solve(1.0, fv, tol=1e-10)
+    g = torch.Generator(device="cpu").manual_seed(3)
+    bad = fv + 50.0 * torch.randn(fv.shape, generator=g, dtype=fv.dtype).to(fv.device)
+    u1, info1 = plan.pcg_solve(1.0, fv, u0=bad, tol=1e-10, u0_guard="finite")
+    u2, info2 = plan.pcg_solve(1.0, fv, u0=bad, tol=1e-10, u0_guard="residual")
+    # a good guess (the solution) passes the residual guard
+    u3, info3 = plan.pcg_solve(1.0, fv, u0=u_plain, tol=1e-9, u0_guard="residual")
+    plan.close()
+    assert info1["status"] == "OK" and not info1["u0_rejected"]
+    assert info2["status"] == "OK" and info2["u0_rejected"]
+    assert info2["iters"] == i_plain["iters"] and torch.equal(u2, u_plain)
+    assert info3["status"] == "OK" and not info3["u0_rejected"] and info3["iters"] <= 1
+    assert rel(u1.cpu().numpy(), u_plain.cpu().numpy()) < 1e-8

@@ -1,0 +1,57 @@
+"""Pins of the stored exact-kernel reference solution (tests/golden/solution_256_s01_a1.*),
+written by tests/golden/make_solution_256.py from the oracle alone: the properties the paper
+fixes for the exact operator hold for it, and its residual, recomputed on sampled rows with
+direct sums of the kernel's definition, is at the level the script recorded."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import csum
+from oracle.features import features_from_image, window_table
+from paper_2407_06834_amd.synth import make_image
+
+HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _load():
+    path = os.path.join(HERE, "solution_256_s01_a1.npy")
+    if not os.path.exists(path):
+        pytest.skip("reference solution not written")
+    meta = {}
+    with open(os.path.join(HERE, "solution_256_s01_a1.txt")) as fh:
+        for line in fh:
+            if not line.startswith("#") and line.strip():
+                k, v = line.split()
+                meta[k] = float(v)
+    side = int(meta["side"])
+    _, f = make_image(int(meta["seed"]), side, side, int(meta["rects"]), int(meta["discs"]),
+                      meta["noise"])
+    return np.load(path), f, meta
+
+
+def test_reference_solution_keeps_mean_and_maximum_principle():
+    # A 1 = 1 and A symmetric: mean(u) = mean(f); the nonnegative kernel gives
+    # min f <= u <= max f (paper Sec. 2.6, maximum principle of the nonlocal problem)
+    u, f, meta = _load()
+    assert u.shape == (f.size,)
+    assert abs(u.mean() - f.mean()) < 1e-12
+    assert f.min() - 1e-12 <= u.min() and u.max() <= f.max() + 1e-12
+    # denoising: the solution is smoother than the data (smaller deviation from its mean)
+    assert np.std(u) < np.std(f)
+    assert meta["relres_true"] < 1e-11
+
+
+def test_reference_solution_residual_on_sampled_rows():
+    u, f, meta = _load()
+    F = features_from_image(f, int(meta["rho"]))
+    wins = window_table(int(meta["rho"]))
+    L = len(wins)
+    sig, wt = [meta["sigma"]] * L, [meta["weight"]] * L
+    rows = np.random.default_rng(5).choice(f.size, 24, replace=False).astype(np.int64)
+    Wu = csum.anova_rows(F, wins, sig, wt, u, rows)
+    W1 = csum.anova_rows(F, wins, sig, wt, np.ones(f.size), rows)
+    r = u[rows] + meta["alpha"] * (W1 * u[rows] - Wu) - f.reshape(-1)[rows]
+    # entries of a residual of norm <= 1e-11 ||f_perp|| (the recorded true residual)
+    fperp = np.linalg.norm(f - f.mean())
+    assert np.max(np.abs(r)) < 1e-10 * fperp
