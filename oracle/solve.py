@@ -9,6 +9,9 @@
                        The forward sum's index range is read as i = 2..N (the printed range
                        stops at N-1, one entry short).
   helmert_dense        U as a dense matrix (small N), for checks.
+  q_dense / q_inv_dense / q_apply / q_inv_apply
+                       the sparse, non-orthogonal change of basis Q of Sec. 4.1.1 for an
+                       eigenvector v (v_1 != 0), its inverse and their O(n) actions.
   pcg_ubasis           the paper's deflated Jacobi-PCG: change of basis with U, x1 = g1
                        (the decoupled eigenvalue of A for the vector 1 is 1 here), CG on the
                        (N-1) block with the preconditioner pi_2(U^T P^-1 U), P = I + alpha
@@ -79,6 +82,55 @@ def helmert_dense(N: int) -> np.ndarray:
         U[i - 1, i - 1] = -(i - 1.0)
         U[:, i - 1] /= np.sqrt(i * (i - 1.0))
     return U
+
+
+# ----------------------------------------------------------------------------- Q basis
+# The sparse change of basis of paper Sec. 4.1.1 for a real eigenvector v with v_1 != 0:
+# q_1 = v and q_i = v_i e_1 - v_1 e_i for i >= 2 (eq. Hermitian_Q_Construction), a symmetric
+# bordered matrix whose inverse is v v^T / (v_1 ||v||^2) - diag(0, 1/v_1, ..., 1/v_1)
+# (eq. Q_inverse_compact).  Both act in O(n).  For v = 1 these are the matrices of Sec. 4.2
+# (eq. QLap).  Q^-1 A Q keeps the eigenvalue of v in its first column with a zero first row,
+# but its (n-1) block is not symmetric, so CG runs in the orthonormal (Helmert) basis instead.
+
+def q_dense(v: np.ndarray) -> np.ndarray:
+    """Q as a dense matrix: first column and row v, lower-right block -v_1 I (small n)."""
+    v = np.asarray(v, dtype=np.float64)
+    if v[0] == 0.0:
+        raise ValueError("q basis: v_1 must be nonzero")
+    n = v.size
+    Q = np.zeros((n, n))
+    Q[:, 0] = v
+    for i in range(1, n):          # column i: v_i e_1 - v_1 e_i
+        Q[0, i] = v[i]
+        Q[i, i] = -v[0]
+    return Q
+
+
+def q_inv_dense(v: np.ndarray) -> np.ndarray:
+    """Q^-1 = v v^T / (v_1 ||v||^2) - diag(0, 1/v_1 ... 1/v_1) (compact form)."""
+    v = np.asarray(v, dtype=np.float64)
+    if v[0] == 0.0:
+        raise ValueError("q basis: v_1 must be nonzero")
+    corr = np.full(v.size, 1.0 / v[0])
+    corr[0] = 0.0
+    return np.outer(v, v) / (v[0] * (v @ v)) - np.diag(corr)
+
+
+def q_apply(v: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Q u = [<u, v>; u_1 v_{2:n} - v_1 u_{2:n}], O(n)."""
+    v = np.asarray(v, dtype=np.float64)
+    out = np.empty_like(v)
+    out[0] = u @ v
+    out[1:] = u[0] * v[1:] - v[0] * u[1:]
+    return out
+
+
+def q_inv_apply(v: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Q^-1 u = (1/v_1) { (<u, v> / ||v||^2) v - [0; u_{2:n}] }, O(n)."""
+    v = np.asarray(v, dtype=np.float64)
+    out = (u @ v) / (v @ v) * v
+    out[1:] -= u[1:]
+    return out / v[0]
 
 
 # ----------------------------------------------------------------------------- CG core
