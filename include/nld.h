@@ -232,6 +232,19 @@ nld_status features_from_image(const void* img, int32_t n1, int32_t n2, int32_t 
 nld_status mis_scores(const void* features, int64_t N, int32_t d, const void* target,
                       nld_prec prec, int32_t bins, double* scores, hipStream_t s);
 
+/* mis_scores without any device allocation, for callers that cannot allocate: code under HIP
+ * graph capture, allocation-free serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, validation and results (bit for bit) as mis_scores.  Its range table and joint
+ * histograms live in a static device array of 1048576 32-bit words (4 MiB) that each device the
+ * library runs on holds until the process ends; a call with 4 (d + 1) + d * B^2 > 1048576
+ * (B = bins, or the default bin count for bins = 0) returns NLD_E_INVAL with nothing launched.
+ * Every call on one device shares that array and leaves its last contents there (the
+ * histograms are cleared by a fill kernel at the start of each call): calls that overlap on one
+ * device (different streams or threads without ordering) race; calls on one stream are
+ * ordered.  Asynchronous. */
+nld_status mis_scores_noalloc(const void* features, int64_t N, int32_t d, const void* target,
+                              nld_prec prec, int32_t bins, double* scores, hipStream_t s);
+
 /* Message describing the last non-OK status returned on this thread. */
 const char* nld_last_error(void);
 

@@ -77,6 +77,24 @@ nld_status mis_scores(const void* features, int64_t N, int32_t d, const void* ta
   });
 }
 
+nld_status mis_scores_noalloc(const void* features, int64_t N, int32_t d, const void* target,
+                              nld_prec prec, int32_t bins, double* scores, hipStream_t s) {
+  if (!features || !target || !scores) return fail(NLD_E_INVAL, "mis_scores_noalloc: null pointer");
+  if (N < 1 || N > 0x7fffffffLL) return fail(NLD_E_INVAL, "mis_scores_noalloc: N must be in [1, 2^31 - 1]");
+  if (d < 1 || d > 4096) return fail(NLD_E_INVAL, "mis_scores_noalloc: d must be in [1, 4096]");
+  if (prec != NLD_FP32 && prec != NLD_FP64) return fail(NLD_E_INVAL, "mis_scores_noalloc: bad precision");
+  if (bins != 0 && (bins < 2 || bins > 64))
+    return fail(NLD_E_INVAL, "mis_scores_noalloc: bins must be 0 or in [2, 64]");
+  const int B = bins ? bins : nld::mis_default_bins(N);
+  if (nld::mis_noalloc_words(d, B) > nld::mis_noalloc_capacity())
+    return fail(NLD_E_INVAL, "mis_scores_noalloc: 4 (d + 1) + d bins^2 exceeds the static scratch "
+                             "of 1048576 words");
+  return guarded("mis_scores_noalloc", [&] {
+    nld::launch_mis_noalloc(features, N, d, target, prec, B, scores, s);
+    return NLD_OK;
+  });
+}
+
 nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t d,
                      const nld_kernel_desc* desc, hipStream_t s) {
   if (!out || !features || !desc) return fail(NLD_E_INVAL, "nfft_plan: null pointer");

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <stdexcept>
 
 #include "nld_internal.h"
@@ -131,8 +132,10 @@ k_mis_score(const unsigned* __restrict__ counts, int B, long long N, double* __r
   if (t == 0) score[j] = acc;
 }
 
+// The three stages on caller-provided scratch: par [2 (d + 1)] doubles, counts [d B^2].
 template <typename T>
-void mis_t(const T* F, long long N, int d, const T* y, int B, double* scores, hipStream_t s) {
+void mis_launch(const T* F, long long N, int d, const T* y, int B, double* scores, double* par,
+                unsigned* counts, hipStream_t s) {
   const int BB = B * B;
   const int G = std::max(1, std::min(d, kMisLds / (4 * BB)));
   const int ngroups = (d + G - 1) / G;
@@ -140,10 +143,6 @@ void mis_t(const T* F, long long N, int d, const T* y, int B, double* scores, hi
   const long long nrb = std::min<long long>(max_rb, std::max(1, 2048 / ngroups));
   const long long chunk = (N + nrb - 1) / nrb;
   const long long ncount = (long long)d * BB;
-  double* par = nullptr;
-  unsigned* counts = nullptr;
-  NLD_HIP(hipMallocAsync((void**)&par, sizeof(double) * 2 * (d + 1), s));
-  NLD_HIP(hipMallocAsync((void**)&counts, sizeof(unsigned) * ncount, s));
   hipLaunchKernelGGL(k_mis_range<T>, dim3(d + 1), dim3(kMisThreads), 0, s, F, y, N, d, B, par);
   hipLaunchKernelGGL(k_mis_zero, dim3((unsigned)((ncount + 255) / 256)), dim3(256), 0, s,
                      counts, ncount);
@@ -152,11 +151,67 @@ void mis_t(const T* F, long long N, int d, const T* y, int B, double* scores, hi
                      chunk, par, counts);
   hipLaunchKernelGGL(k_mis_score, dim3(d), dim3(kMisThreads), 0, s, counts, B, N, scores);
   NLD_HIP(hipGetLastError());
+}
+
+template <typename T>
+void mis_t(const T* F, long long N, int d, const T* y, int B, double* scores, hipStream_t s) {
+  double* par = nullptr;
+  unsigned* counts = nullptr;
+  NLD_HIP(hipMallocAsync((void**)&par, sizeof(double) * 2 * (d + 1), s));
+  NLD_HIP(hipMallocAsync((void**)&counts, sizeof(unsigned) * (size_t)d * B * B, s));
+  mis_launch<T>(F, N, d, y, B, scores, par, counts, s);
   NLD_HIP(hipFreeAsync(counts, s));
   NLD_HIP(hipFreeAsync(par, s));
 }
 
+// ---------------------------------------------------------------------------- no allocation
+// Scratch of mis_scores_noalloc: the range table (4 (d + 1) words) followed by the joint
+// histograms (d B^2 words) in one file-scope device array, which every device the library runs
+// on holds until the process ends.  In host code `scratch` names a host-side stand-in, not the
+// device copy: its device address is looked up once per device (scratch_on_device) and only
+// that address is handed to kernels.
+constexpr long long kMisScratchWords = 1LL << 20;   // 4 MiB
+static __device__ __align__(256) unsigned scratch[kMisScratchWords];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned* g_scratch_dev[kMaxScratchDevices] = {};
+
+unsigned* scratch_on_device() {
+  int dev = 0;
+  NLD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) throw std::runtime_error("device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) throw HipError{e, "hipGetSymbolAddress(scratch)"};
+    g_scratch_dev[dev] = static_cast<unsigned*>(p);
+  }
+  return g_scratch_dev[dev];
+}
+
 }  // namespace
+
+long long mis_noalloc_words(int d, int bins) {
+  return 4LL * (d + 1) + (long long)d * bins * bins;
+}
+
+long long mis_noalloc_capacity() { return kMisScratchWords; }
+
+void launch_mis_noalloc(const void* F, long long N, int d, const void* y, nld_prec prec, int bins,
+                        double* scores, hipStream_t s) {
+  if (bins < 2 || bins > 64) throw std::invalid_argument("bins out of range");
+  if (mis_noalloc_words(d, bins) > kMisScratchWords)
+    throw std::invalid_argument("4 (d + 1) + d bins^2 exceeds the static scratch of 1048576 words");
+  unsigned* base = scratch_on_device();
+  double* par = reinterpret_cast<double*>(base);                 // 256-byte aligned
+  unsigned* counts = base + 4LL * (d + 1);
+  if (prec == NLD_FP32)
+    mis_launch<float>((const float*)F, N, d, (const float*)y, bins, scores, par, counts, s);
+  else
+    mis_launch<double>((const double*)F, N, d, (const double*)y, bins, scores, par, counts, s);
+}
 
 int mis_default_bins(long long N) {
   int B = 1;

@@ -280,6 +280,11 @@ void launch_features(const void* img, int n1, int n2, int rho, int with_pos, nld
 int mis_default_bins(long long N);
 void launch_mis(const void* F, long long N, int d, const void* y, nld_prec prec, int bins,
                 double* scores, hipStream_t s);
+// the same scores on the library's static device scratch (no allocation); words needed and held
+long long mis_noalloc_words(int d, int bins);
+long long mis_noalloc_capacity();
+void launch_mis_noalloc(const void* F, long long N, int d, const void* y, nld_prec prec, int bins,
+                        double* scores, hipStream_t s);
 
 // fast summation (nfft.hip)
 size_t plane_lds_bytes(int n);   // LDS of the fused plane convolution for n = 64 or 128

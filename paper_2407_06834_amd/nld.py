@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NOCONV", 
 # Entry points declared in include/nld.h
 SYMBOLS = ("nfft_plan", "nfft_plan_update_kernel", "nfft_plan_destroy", "nfft_plan_window_info", "nfft_plan_size",
            "degree_vector", "anova_matvec", "laplacian_matvec", "pcg_solve", "pcg_solve_batched", "adjoint_solve",
-           "features_from_image", "mis_scores", "nld_last_error")
+           "features_from_image", "mis_scores", "mis_scores_noalloc", "nld_last_error")
 
 
 class KernelDesc(ctypes.Structure):
@@ -96,6 +96,7 @@ def load() -> ctypes.CDLL:
                           ctypes.POINTER(PcgInfo), P],
         "features_from_image": [P, I32, I32, I32, I32, I32, P, P],
         "mis_scores": [P, I64, I32, P, I32, I32, P, P],
+        "mis_scores_noalloc": [P, I64, I32, P, I32, I32, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -326,9 +327,12 @@ def window_table(rho: int, with_pos: bool = True):
     return wins
 
 
-def mis_scores(features: torch.Tensor, target: torch.Tensor, bins: int = 0, stream=None):
+def mis_scores(features: torch.Tensor, target: torch.Tensor, bins: int = 0, stream=None,
+               out=None, noalloc: bool = False):
     """Mutual information score (float64, on the GPU) of every feature row of the SoA matrix
-    (d, N) against the target (N); see mis_scores in nld.h."""
+    (d, N) against the target (N); see mis_scores in nld.h.  noalloc=True calls
+    mis_scores_noalloc (the library allocates nothing; pass `out` to allocate nothing here
+    either)."""
     if features.dim() != 2 or not features.is_cuda:
         raise ValueError("features: expected a 2-D CUDA tensor (d, N)")
     if features.dtype not in (torch.float32, torch.float64):
@@ -336,11 +340,20 @@ def mis_scores(features: torch.Tensor, target: torch.Tensor, bins: int = 0, stre
     d, N = features.shape
     features = features.contiguous()
     y = _vec(target.reshape(-1), N, features.dtype, "target")
-    out = torch.empty(d, dtype=torch.float64, device=features.device)
+    if out is None:
+        out = torch.empty(d, dtype=torch.float64, device=features.device)
+    _vec(out, d, torch.float64, "out")          # validates the output vector
     prec = NLD_FP32 if features.dtype == torch.float32 else NLD_FP64
-    _check(load().mis_scores(ctypes.c_void_p(features.data_ptr()), N, d, y, prec, int(bins),
-                             ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    fn = load().mis_scores_noalloc if noalloc else load().mis_scores
+    _check(fn(ctypes.c_void_p(features.data_ptr()), N, d, y, prec, int(bins),
+              ctypes.c_void_p(out.data_ptr()), _stream(stream)))
     return out
+
+
+def mis_scores_noalloc(features: torch.Tensor, target: torch.Tensor, bins: int = 0, stream=None,
+                       out=None):
+    """mis_scores_noalloc of nld.h: mis_scores on the library's static scratch."""
+    return mis_scores(features, target, bins, stream, out=out, noalloc=True)
 
 
 def mis_window_table(features: torch.Tensor, target: torch.Tensor, bins: int = 0, size: int = 3,
