@@ -19,7 +19,11 @@ namespace nld {
 
 namespace {
 
-constexpr int kTileChunk = 2048;     // nodes per spreading / gathering workgroup
+constexpr int kTileChunk = 4096;     // nodes per spreading / gathering workgroup (default)
+int tile_chunk() {
+  const char* e = std::getenv("NLD_TILE_CHUNK");
+  return e ? std::max(64, std::min(1 << 20, std::atoi(e))) : kTileChunk;
+}
 constexpr int kMaxCellBits = 16;     // sort key = global tile << cell_bits | cell within the tile
 
 template <typename T>
@@ -850,6 +854,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   std::vector<TileJob> jobs;
   std::vector<int> slot0(tile_total, 0), nslot(tile_total, 0);
   int slots = 0;
+  const long long chunk = tile_chunk();
   for (int g = 0; g < 3; ++g) {
     P.tjob_begin[g] = (int)jobs.size();
     for (int l = 0; l < L; ++l) {
@@ -861,8 +866,8 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
         const long long b0 = ht[gt], b1 = ht[gt + 1];
         if (b1 == b0) continue;
         slot0[gt] = slots;
-        for (long long c = b0; c < b1; c += kTileChunk) {
-          jobs.push_back(TileJob{l, tl, (int)c, (int)std::min(b1, c + kTileChunk), slots});
+        for (long long c = b0; c < b1; c += chunk) {
+          jobs.push_back(TileJob{l, tl, (int)c, (int)std::min(b1, c + chunk), slots});
           ++slots;
           ++nslot[gt];
         }
