@@ -229,6 +229,34 @@ def fast_sigma_derivative_window(X, v, sigma, M, n, m):
     return gather(h, u, m, b)
 
 
+def window_matrix_nfft(X: np.ndarray, sigma: float, M: int, n: int, m: int) -> np.ndarray:
+    """The dense N x N matrix of fast_gauss_window for one window X (t, N), for small N.
+
+    The summation is W~ = B C B^T with B the spreading matrix and C the circulant of the
+    multiplier; both factor over the kept dimensions (the window is a tensor product of one
+    window per dimension, the multiplier a product of per-dimension multipliers), so
+    W~ = T_1 o ... o T_t (entrywise product) with T_d = B_d C_d B_d^T, B_d (N x n) the 2m tap
+    weights of dimension d and C_d[c, c'] = sum_k c_k e^{2 pi i k (c - c') / n} the real
+    circulant of that dimension's multiplier."""
+    kept, centres, scales, st = torus_scaling(X, sigma, M)
+    N = X.shape[1]
+    if not kept:
+        return np.ones((N, N))
+    b = kb_shape(n, M)
+    Wt = np.ones((N, N))
+    rows = np.arange(N)
+    for d, c, s, s_t in zip(kept, centres, scales, st):
+        u = grid_coords(((X[d] - c) * s)[None, :], n)
+        cells, w = _taps(u, n, m, b)                      # (1, N, 2m)
+        B = np.zeros((N, n))
+        for tap in range(2 * m):
+            np.add.at(B, (rows, cells[0, :, tap]), w[0, :, tap])
+        col = (np.fft.ifft(conv_multiplier(n, M, m, s_t)) * n).real   # C[c, 0] = col[c]
+        C = col[(np.arange(n)[:, None] - np.arange(n)[None, :]) % n]
+        Wt *= B @ C @ B.T
+    return Wt
+
+
 def anova_matvec_nfft(F, wins, sigmas, weights, v, M, n, m):
     """W~ v = sum_l w_l K~_l v with one fast Gauss summation per window (Sec. 3)."""
     y = np.zeros(F.shape[1])

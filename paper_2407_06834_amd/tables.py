@@ -50,7 +50,7 @@ def _windows(F, img, rho):
     return nld.window_table(rho, with_pos=False)
 
 
-def _plan(img, rho: int, sigma255: float, tol: float, times=None):
+def _plan(img, rho: int, sigma255: float, tol: float, times=None, **plan_kw):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     F = nld.features_from_image(img, rho, with_pos=False)
@@ -58,7 +58,7 @@ def _plan(img, rho: int, sigma255: float, tol: float, times=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     L = len(wins)
-    plan = nld.Plan(F, wins, [sigma255 / 255.0] * L, [1.0 / L] * L, matvec_tol=tol)
+    plan = nld.Plan(F, wins, [sigma255 / 255.0] * L, [1.0 / L] * L, matvec_tol=tol, **plan_kw)
     if times is not None:
         plan.degree_vector()
         torch.cuda.synchronize()
@@ -108,11 +108,12 @@ def solution_table(sides):
     return rows
 
 
-def iterations_table(sides, lambdas=LAMBDAS):
+def iterations_table(sides, lambdas=LAMBDAS, plan_kw=None):
+    """plan_kw: fixed summation parameters (bandwidth, cutoff); default: chosen for 1e-9."""
     rows = []
     for side in sides:
         img = _image(side)
-        plan, L = _plan(img, 5, 30.0, 1e-9)
+        plan, L = _plan(img, 5, 30.0, 1e-9, **(plan_kw or {}))
         row = dict(side=side, n=side * side, windows=L)
         for lam in lambdas:
             alpha = 1e-2 / lam

@@ -27,3 +27,77 @@ def test_tables_small():
             assert pa_u <= pa
     # without a preconditioner CG stalls once lambda is small
     assert it["lambda=1e-09"][0] == "x"
+
+
+def _oracle_iterations(f, M, m, lambdas):
+    """The iteration-table protocol (paper Sec. 5.4) on the oracle: 11x11 patches without
+    position in the oracle's MIS windows (L = 41), sigma = 30/255, weights 1/L, mu = 1e-2,
+    tolerance 1e-8, at most 30 iterations, x0 = f; columns none / P_a / P_b' in the original
+    basis, then in the U basis (projector form).  Two operators: the exact dense kernel, and
+    the dense matrix of the oracle's NFFT summation with the given (M, n = 2M, m)."""
+    import numpy as np
+    from oracle import kernel as K
+    from oracle import mis as OM
+    from oracle import nfft as ON
+    from oracle import solve as OS
+    from oracle.features import features_from_image
+    F = features_from_image(f, 5, with_pos=False)
+    wins = OM.mis_windows(OM.mis_scores(F, f.reshape(-1)))
+    L = len(wins)
+    sig, wts = [30.0 / 255.0] * L, [1.0 / L] * L
+    ops = {"exact": K.anova_dense(F, wins, sig, wts),
+           "nfft": sum(w * ON.window_matrix_nfft(F[list(win)], s, M, 2 * M, m)
+                       for win, s, w in zip(wins, sig, wts))}
+    d2 = K.l2_window_degree(F, wins, sig, wts)
+    fv = f.reshape(-1)
+    out = {}
+    for name, W in ops.items():
+        D = W.sum(axis=1)
+        eta = D - 1.0
+        Lap = np.diag(D) - W
+        table = {}
+        for lam in lambdas:
+            a = 1e-2 / lam
+            A = np.eye(fv.size) + a * Lap
+            cols = []
+            for defl in (False, True):
+                for pre in ("none", "jacobi", "l2"):
+                    P = (np.ones_like(fv) if pre == "none" else
+                         1.0 + a * eta if pre == "jacobi" else K.precond_l2_anova(eta, d2, a))
+                    if defl:
+                        _, it, rr, _ = OS.pcg_projector(lambda v: A @ v, fv, eta, a, 1e-8, 30, P=P)
+                    else:
+                        _, it, rr = OS.pcg_jacobi(lambda v: A @ v, fv, eta, a, 1e-8, 30, P=P)
+                    cols.append(it if rr <= 1e-8 else "x")
+            table[lam] = cols
+        out[name] = (table, wins)
+    return out
+
+
+def test_iteration_table_matches_the_oracle():
+    """64 x 64, L = 41, M = 64, m = 8: the library's six columns per lambda equal the oracle's
+    with the same NFFT operator to +-1 iteration; the oracle's exact-kernel operator gives the
+    same counts, so the growth of the U-basis counts as lambda falls is a property of the
+    problem, not of the approximation."""
+    torch_gpu()
+    from paper_2407_06834_amd import nld, tables
+    from paper_2407_06834_amd.synth import make_image
+    M, m = 64, 8
+    hip = tables.iterations_table([64], plan_kw=dict(bandwidth=M, cutoff=m))[0]
+    _, f = make_image(7, 64, 64, 8, 5, 0.1)          # the protocol's image at side 64
+    orc = _oracle_iterations(f, M, m, tables.LAMBDAS)
+    img = tables._image(64)
+    F = nld.features_from_image(img, 5, with_pos=False)
+    assert nld.mis_window_table(F, img.reshape(-1))[0] == orc["nfft"][1]
+
+    def close(a, b):
+        return a == b or (a != "x" and b != "x" and abs(a - b) <= 1)
+
+    for lam in tables.LAMBDAS:
+        got = hip[f"lambda={lam:g}"]
+        ref = orc["nfft"][0][lam]
+        exact = orc["exact"][0][lam]
+        print(f"lambda {lam:g}: library {got}, oracle NFFT {ref}, oracle exact {exact}", flush=True)
+        assert all(close(a, b) for a, b in zip(got, ref)), (lam, got, ref)
+        # the exact operator: same counts wherever both converge
+        assert all(close(a, b) for a, b in zip(got, exact) if a != "x" and b != "x"), (lam, got, exact)

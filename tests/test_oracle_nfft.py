@@ -195,3 +195,20 @@ def test_sigma_derivative_summation_against_dense():
         y = nfft.fast_sigma_derivative_window(X, v, 0.15, 48, 96, 6)
         yd = sigma_derivative_kernel(F, list(range(t)), 0.15) @ v
         assert np.linalg.norm(y - yd) / np.linalg.norm(yd) < 1e-7
+
+
+def test_dense_window_matrix_equals_fast_summation_and_is_psd():
+    # the dense form B C B^T (entrywise product of per-dimension factors) is the same linear
+    # map as the staged summation, symmetric and positive semidefinite, and within the
+    # truncation error of the exact Gaussian kernel
+    rng = np.random.default_rng(21)
+    X = rng.uniform(0.0, 1.0, (3, 150))
+    X[2] = 0.37                              # a dropped (constant) dimension
+    sigma, M, n, m = 0.15, 32, 64, 6
+    Wt = nfft.window_matrix_nfft(X, sigma, M, n, m)
+    v = rng.standard_normal(150)
+    np.testing.assert_allclose(Wt @ v, nfft.fast_gauss_window(X, v, sigma, M, n, m), atol=1e-11)
+    np.testing.assert_allclose(Wt, Wt.T, atol=1e-13)
+    assert np.linalg.eigvalsh(Wt).min() > -1e-10 * np.abs(Wt).max()
+    Kx = K.window_kernel_dense(X, [0, 1, 2], sigma)
+    assert np.abs(Wt - Kx).max() < 1e-5
