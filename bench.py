@@ -1,28 +1,37 @@
-"""Benchmark: NFFT nonlocal denoising of a 512 x 512 synthetic image on one MI355X.
+"""Benchmark: learned warm start vs plain deflated PCG on 2048 x 2048 synthetic images, one MI355X.
 
-One step = the whole hot path over one image: features (5x5 patch + position, 27 dims),
-for each kernel width sigma in {0.05, 0.1, 0.2} a plan over 9 windows of 3 features
-(torus scaling, tile sort, Fourier multipliers) and the degree vector, and for each
-alpha in {0.1, 1, 10} one deflated Jacobi-PCG solve of (I + alpha L) u = f to relative
-residual 1e-6: 9 denoised images per step.  value = 9 * N / step time (Mpixel/s).
+One step = one 2048 x 2048 evaluation image (seeded: 20 rectangles, 12 discs, noise 0.1; alpha
+~ logU[0.05, 20] and sigma_l ~ U[0.05, 0.2] per window, drawn per image) through the whole hot
+path three times:
+  plain  features (5x5 patch + position, 27 dims), plan over 9 windows of 3 (torus scaling, tile
+         sort, Fourier multipliers, bandwidth per window for a 1e-4 product, m = 4, FP32 with
+         FP64 reductions) and degree vector, then deflated Jacobi PCG from u0 = f to relative
+         residual 1e-6;
+  warm   the same features, plan and degree vector, the warm-start network (BF16 MFMA kernels)
+         predicting u0 from (f, alpha, sigma_l), then the same PCG from the energy-optimal
+         multiple b Pi u0 of its output (no extra product; a non-finite u0 is replaced by f).
+  zero   control without the network: the same PCG from u = mean(f) 1.
+value = Mpixel/s of the warm path (pixels / (plan + network + PCG time)); the plain path's
+Mpixel/s and the ratio are in `config`.  Both solves run on the same plan; the plan time counts in
+both.  Inputs are uploaded before the timed region.
 
-Printed as one JSON line; also carries the roofline of the dominant operation (the NFFT
-Laplacian product inside CG, timed with HIP events by the library on the solve's stream)
-and a CPU baseline (the FP64 NFFT oracle, one product timed on the host, extrapolated).
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--weights FILE] [--no-cpu-baseline]
+                    [--no-c2] [--profile-copy]
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64] [--no-cpu-baseline]
-                    [--profile-copy]
-
-`roofline.traffic` is the HBM traffic of one product measured with rocprofv3 counters
-(FETCH_SIZE and WRITE_SIZE summed over the product's kernels, each scaled by what the counter
-reads for a device copy of 256 MiB; --profile-copy runs that copy after the timed steps); it is
-reported only while the kernel sources hash to the value recorded with the measurement.
+`roofline` is the Laplacian product inside the timed solves (event-timed by the library on the
+solve's stream).  `roofline_c2` is the 512 x 512 FP32 product of the survey's HBM-bound case
+(9 windows, M = 64, n = 128, m = 4), timed the same way in a short section after the timed steps
+(--no-c2 skips it).  `traffic` fields are HBM bytes from rocprofv3 counters (FETCH_SIZE +
+WRITE_SIZE, copy-scaled), reported only while the kernel sources hash to the recorded value.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
+import statistics
 import sys
 import time
 
@@ -30,45 +39,69 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+SIDE = 2048
+RHO = 2
+TOL = 1e-6
+EVAL_SEED0 = 300
+WEIGHTS = os.path.join(ROOT, "paper_2407_06834_amd", "weights", "warmstart_c5.npy")
 
-# HBM bytes of one FP32 Laplacian product on this workload, from the rocprofv3 counter runs kept
-# in profiles/nfft_laplacian_512_fp32_hbm_traffic.md, valid for the kernel sources of that hash
-TRAFFIC = {"sha1": "6418c9213667ee5024d0887cd5988a2525a911c2", "bytes": 834913906}
+# HBM bytes per product from the rocprofv3 counter runs in profiles/ (valid for the kernel
+# sources of the recorded hash)
+TRAFFIC = {
+    "c2_512": {"sha1": "6418c9213667ee5024d0887cd5988a2525a911c2", "bytes": 834913906},
+    "c5_2048": {"sha1": None, "bytes": None},
+}
 KERNEL_SOURCES = ("paper_2407_06834_amd/csrc/nfft.hip", "paper_2407_06834_amd/csrc/plan.hip",
                   "paper_2407_06834_amd/csrc/nld_internal.h", "paper_2407_06834_amd/csrc/nld_device.h")
 
 
 def kernel_sha1() -> str:
-    import hashlib
     h = hashlib.sha1()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
-N1 = N2 = 512
-RHO = 2
-SIGMAS = (0.05, 0.1, 0.2)
-ALPHAS = (0.1, 1.0, 10.0)
-M = 64
-TOL = 1e-6
 
 
-def matvec_bytes(N: int, L: int, t: int, G: int, b: int) -> int:
-    """Algorithmic HBM bytes of one Laplacian product: per window, node coordinates and
-    node index read twice, the input read, the window result written and read once, the
-    grid written by the spread, read and written by each of the t convolution passes and
-    read by the gather; plus the epilogue (D in FP64, v in, result out)."""
-    per_window = N * (2 * t * b + 8 + 3 * b) + G * b * (2 + 2 * t)
-    return L * per_window + N * (8 + 2 * b)
+def product_bytes(N: int, grids, b: int = 4) -> int:
+    """Algorithmic HBM bytes of one Laplacian product: per 3-D window with n^3 grid cells, node
+    coordinates and node index read twice, the input read, the window result written and read
+    once, the grid written by the spread, read and written by each of the 3 convolution passes
+    and read by the gather; plus the epilogue (D in FP64, v in, result out)."""
+    t = 3
+    return sum(N * (2 * t * b + 8 + 3 * b) + (n ** 3) * b * (2 + 2 * t) for n in grids) + \
+        N * (8 + 2 * b)
+
+
+def product_flops(N: int, grids, m: int = 4) -> float:
+    """Algorithmic FLOPs of one product: 2 flops per tap in spreading and in gathering
+    ((2m)^3 taps per node and window), and per window 3 passes of n^2 lines, each a real
+    circulant convolution of 5 n log2 n + n flops."""
+    import math
+    w3 = (2 * m) ** 3
+    return float(sum(4 * N * w3 + 3 * n * n * (5 * n * math.log2(n) + n) for n in grids))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", choices=("f32", "f64"), default="f32")
+    ap.add_argument("--weights", default=WEIGHTS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--profile-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -81,63 +114,90 @@ def main():
     import torch
 
     from paper_2407_06834_amd import nld
-    from paper_2407_06834_amd.synth import make_image
+    from paper_2407_06834_amd.cnn import WarmStartNet
+    from paper_2407_06834_amd.warmstart import cond_of, draw_problem
 
     nld.load()
-    dev = torch.device("cuda:0")
-    dtype = torch.float32 if args.dtype == "f32" else torch.float64
-    m = 4 if args.dtype == "f32" else 8
-    _, f = make_image(1, N1, N2, 20, 12, 0.1)
-    img = torch.tensor(f, dtype=dtype, device=dev)
-    fv = img.reshape(-1)
-    N = N1 * N2
+    if not os.path.exists(args.weights):
+        raise SystemExit(f"bench.py: network weights not found at {args.weights} "
+                         "(python -m paper_2407_06834_amd.warmstart --save FILE writes them)")
+    net = WarmStartNet(n_cond=10, seed=0)
+    net.set_params(np.load(args.weights))
     wins = nld.window_table(RHO)
     L = len(wins)
-    u = torch.empty_like(fv)
-    stream = torch.cuda.current_stream()
+    N = SIDE * SIDE
 
-    def step(record):
+    # inputs: seeded evaluation images, uploaded before the timed region
+    total = args.warmup + args.steps
+    probs = [draw_problem(EVAL_SEED0 + k, side=SIDE, noise=0.1) for k in range(total)]
+    imgs = [torch.tensor(p["f"], dtype=torch.float32, device="cuda") for p in probs]
+    conds = [np.array([cond_of(p["alpha"], p["sigma"])]) for p in probs]
+    torch.cuda.synchronize()
+
+    def step(k, rec):
+        p, img = probs[k], imgs[k]
+        fv = img.reshape(-1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         F = nld.features_from_image(img, RHO)
-        for sigma in SIGMAS:
-            plan = nld.Plan(F, wins, [sigma] * L, [1.0] * L, bandwidth=M, cutoff=m)
-            for alpha in ALPHAS:
-                _, info = plan.pcg_solve(alpha, fv, tol=TOL, maxit=500, out=u, timing=record)
-                if record is not None:
-                    record.append((sigma, alpha, info))
-            plan.close()
+        plan = nld.Plan(F, wins, p["sigma"], [1.0] * L, cutoff=4, matvec_tol=1e-4)
+        plan.degree_vector()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, ip = plan.pcg_solve(p["alpha"], fv, tol=TOL, maxit=1000, timing=rec is not None)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        u0 = net.predict(img.reshape(1, SIDE, SIDE), conds[k]).reshape(-1)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        _, iw = plan.pcg_solve(p["alpha"], fv, u0=u0, tol=TOL, maxit=1000,
+                               timing=rec is not None, u0_guard="scaled")
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        # control without the network: the zero start u = mean(f) 1
+        _, iz = plan.pcg_solve(p["alpha"], fv, u0=torch.full_like(fv, float(fv.mean())), tol=TOL,
+                               maxit=1000)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        grids = [plan.window_info(l).grid for l in range(L)]
+        plan.close()
+        if rec is not None:
+            rec.append(dict(plan=t1 - t0, plain=t2 - t1, net=t3 - t2, warm=t4 - t3, zero=t5 - t4,
+                            ip=ip, iw=iw, iz=iz, grids=grids))
 
-    for _ in range(args.warmup):
-        step(None)
-    infos = []
+    for k in range(args.warmup):
+        step(k, None)
+    recs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(infos)
+    for k in range(args.warmup, total):
+        step(k, recs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    if args.profile_copy:
-        a = torch.ones(64 * 1024 * 1024, device=dev)   # 256 MiB, the counters' scale reference
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    mpix = 9 * N / (ms_step * 1e-3) / 1e6
-    bad = [i for i in infos if i[2]["status"] != "OK"]
 
-    # roofline of the NFFT Laplacian product (dominant operation): algorithmic bytes over the
-    # mean duration of the products timed inside the solves of the timed steps
-    b = 4 if args.dtype == "f32" else 8
-    n_grid = 2 * M
-    bytes_mv = matvec_bytes(N, L, 3, n_grid ** 3, b)
-    timed = [(i["ms_matvec"], i["matvecs_timed"]) for _, _, i in infos if i["matvecs_timed"] > 0]
-    ms_mv = sum(a * k for a, k in timed) / max(1, sum(k for _, k in timed))
-    achieved = bytes_mv / (ms_mv * 1e-3) / 1e9 if ms_mv > 0 else 0.0
-    iters = [i["iters"] for _, _, i in infos]
+    t_plain = sum(r["plan"] + r["plain"] for r in recs)
+    t_warm = sum(r["plan"] + r["net"] + r["warm"] for r in recs)
+    t_zero = sum(r["plan"] + r["zero"] for r in recs)
+    mpix_plain = N * len(recs) / t_plain / 1e6
+    mpix_warm = N * len(recs) / t_warm / 1e6
+    mpix_zero = N * len(recs) / t_zero / 1e6
+    bad = sum(1 for r in recs for i in (r["ip"], r["iw"], r["iz"]) if i["status"] != "OK")
 
+    # dominant kernel: the Laplacian product inside the timed solves
+    nb = nf = ms = 0.0
+    for r in recs:
+        for i in (r["ip"], r["iw"]):
+            k = i["matvecs_timed"]
+            nb += k * product_bytes(N, r["grids"])
+            nf += k * product_flops(N, r["grids"])
+            ms += k * i["ms_matvec"]
+    n_prod = sum(i["matvecs_timed"] for r in recs for i in (r["ip"], r["iw"]))
+    sha = kernel_sha1()
+    tr = TRAFFIC["c5_2048"]
     out = {
-        "metric": "Mpixel/s denoised at rel-res 1e-6 (plain deflated Jacobi PCG); matvec GB/s",
-        "value": round(mpix, 4),
+        "metric": "Mpixel/s denoised at rel-res 1e-6, learned warm-start vs plain PCG; matvec GB/s",
+        "value": round(mpix_warm, 4),
         "unit": "Mpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -146,60 +206,139 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.dtype,
+        "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "512x512 synthetic image (20 rectangles, 12 discs, noise 0.1), 5x5 "
-                        "patch + position features in 9 windows of 3, sigma in {0.05,0.1,0.2} x "
-                        "alpha in {0.1,1,10}, M=64, n=128, m=%d, deflated Jacobi PCG to 1e-6" % m,
-            "pixels_per_step": 9 * N,
-            "mean_iters": round(float(np.mean(iters)), 2),
-            "solves_not_converged": len(bad),
+            "workload": "2048x2048 synthetic images (20 rectangles, 12 discs, noise 0.1; seeds "
+                        "%d..%d), alpha ~ logU[0.05,20], sigma_l ~ U[0.05,0.2], 5x5 patch + "
+                        "position in 9 windows of 3, FP32 NFFT (m=4, bandwidth per window for a "
+                        "1e-4 product) with FP64 reductions, deflated Jacobi PCG to 1e-6; warm "
+                        "start from the 5-layer BF16 network vs plain PCG from u0=f"
+                        % (EVAL_SEED0 + args.warmup, EVAL_SEED0 + total - 1),
+            "value_is": "warm-start path: plan + degree + network + PCG",
+            "mpix_warm": round(mpix_warm, 4),
+            "mpix_plain": round(mpix_plain, 4),
+            "speedup_warm_vs_plain": round(t_plain / t_warm, 4),
+            "mean_iters_plain": round(float(np.mean([r["ip"]["iters"] for r in recs])), 2),
+            "mean_iters_warm": round(float(np.mean([r["iw"]["iters"] for r in recs])), 2),
+            "mpix_zero_start": round(mpix_zero, 4),
+            "mean_iters_zero_start": round(float(np.mean([r["iz"]["iters"] for r in recs])), 2),
+            "zero_start_note": "control without the network: PCG from u = mean(f) 1",
+            "u0_rejected": int(sum(r["iw"]["u0_rejected"] for r in recs)),
+            "ms_plan_mean": round(1e3 * float(np.mean([r["plan"] for r in recs])), 3),
+            "ms_net_mean": round(1e3 * float(np.mean([r["net"] for r in recs])), 3),
+            "pixels_per_step": N,
+            "solves_not_converged": bad,
         },
         "roofline": {
-            "kernel": "NFFT Laplacian product (spread, fold, 3 FFT passes, gather, reduce)",
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (round(TRAFFIC["bytes"] / 1e9, 4)
-                        if TRAFFIC["sha1"] is not None and TRAFFIC["sha1"] == kernel_sha1() and
-                        args.dtype == "f32" else None),
+            "kernel": "NFFT Laplacian product at 2048x2048 (spread, fold, FFT passes, gather, "
+                      "reduce), inside the timed solves",
+            "bound": "alu",
+            "achieved": round(nf / (ms * 1e-3) / 1e12, 3) if ms > 0 else 0.0,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(nf / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4) if ms > 0 else 0.0,
+            "traffic": (round(tr["bytes"] / 1e9, 4) if tr["sha1"] == sha and tr["bytes"] else None),
             "traffic_unit": "GB per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-            "bytes_per_launch": bytes_mv,
-            "ms_per_launch": round(ms_mv, 4),
+            "flops_per_launch": round(nf / max(1, n_prod)),
+            "bytes_per_launch": round(nb / max(1, n_prod)),
+            "hbm_gbs": round(nb / (ms * 1e-3) / 1e9, 1) if ms > 0 else 0.0,
+            "hbm_frac": round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else 0.0,
+            "ms_per_launch": round(ms / max(1, n_prod), 4),
+            "launches": n_prod,
         },
     }
+    if not args.no_c2:
+        out["roofline_c2"] = c2_product(nld, torch, sha)
+    if args.profile_copy:
+        a = torch.ones(64 * 1024 * 1024, device="cuda")   # 256 MiB, the counters' scale reference
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(f, wins, m, iters)
+        out["cpu_baseline"] = cpu_baseline(probs[args.warmup], out["config"])
+    net.close()
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(f, wins, m, iters):
-    """The FP64 NFFT oracle as it stands: the fast Gauss summation of one window (of the 9) at
-    sigma = 0.1 timed on one host core, extrapolated to a solve as 9 windows per product and
-    (iterations + 2) products per solve."""
+def c2_product(nld, torch, sha):
+    """The 512 x 512 FP32 product of the survey's HBM-bound case (image seed 1: 20 rectangles,
+    12 discs, noise 0.1; 9 windows, sigma 0.1, M = 64, n = 128, m = 4), event-timed by the
+    library inside two deflated PCG solves (alpha = 1, tol 1e-6)."""
+    from paper_2407_06834_amd.synth import make_image
+    _, f = make_image(1, 512, 512, 20, 12, 0.1)
+    img = torch.tensor(f, dtype=torch.float32, device="cuda")
+    F = nld.features_from_image(img, RHO)
+    wins = nld.window_table(RHO)
+    plan = nld.Plan(F, wins, [0.1] * 9, [1.0] * 9, bandwidth=64, cutoff=4)
+    plan.pcg_solve(1.0, img.reshape(-1), tol=TOL, maxit=500)
+    _, info = plan.pcg_solve(1.0, img.reshape(-1), tol=TOL, maxit=500, timing=True)
+    plan.close()
+    N = 512 * 512
+    bts = product_bytes(N, [128] * 9)
+    ms = info["ms_matvec"]
+    tr = TRAFFIC["c2_512"]
+    return {"kernel": "NFFT Laplacian product at 512x512 (9 windows, M=64, n=128, m=4, FP32)",
+            "bound": "hbm", "achieved": round(bts / (ms * 1e-3) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(bts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": (round(tr["bytes"] / 1e9, 4) if tr["sha1"] == sha else None),
+            "traffic_unit": "GB per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "bytes_per_launch": bts, "ms_per_launch": round(ms, 4),
+            "launches": info["matvecs_timed"], "timed": "after the timed steps"}
+
+
+def cpu_baseline(p, cfg):
+    """The FP64 NFFT oracle as it stands, on a bounded sample: the fast Gauss summation of one
+    3-dim window (window 2 of 9, that image's sigma) over the central 128x128 and 512x512 crops
+    of the first timed image's features, M = 64, n = 128, m = 4, median of 3 on one thread and
+    on all host threads; the time per node-window is fitted as a + b N on the two crops and
+    extrapolated to a solve: 9 windows x 2048^2 nodes per product, (mean iterations + 2)
+    products per solve (plain path)."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     from oracle import nfft as ON
     from oracle.features import features_from_image as o_features
 
-    F = o_features(f, RHO)
-    v = np.random.default_rng(0).standard_normal(F.shape[1])
-    t0 = time.perf_counter()
-    ON.fast_gauss_window(F[wins[1]], v, 0.1, M, 2 * M, m)
-    t_win = time.perf_counter() - t0
-    t_mv = t_win * len(wins)
-    solves = [(it + 2) * t_mv for it in iters]
-    sec_per_solve = float(np.mean(solves))
-    N = F.shape[1]
-    return {"value": round(N / sec_per_solve / 1e6, 6), "unit": "Mpixel/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "FP64 NFFT fast Gauss summation of one 3-dim window (512x512 nodes, M=64, "
-                      "n=128, m=%d) in numpy on one host core, %.1f s; extrapolated to a solve as "
-                      "9 windows per product and (iterations + 2) products at the GPU's mean "
-                      "iteration count" % (m, t_win)}
+    f = p["f"]
+    c0 = SIDE // 2
+    crops = {}
+    for h in (128, 512):
+        sub = f[c0 - h // 2:c0 + h // 2, c0 - h // 2:c0 + h // 2]
+        crops[h] = o_features(sub, RHO)[[3, 4, 5]]      # window 2 of the fixed grouping
+    sig = p["sigma"][1]
+    rng = np.random.default_rng(0)
+
+    def med(threads):
+        ts = {}
+        with threadpool_limits(limits=threads):
+            for h, X in crops.items():
+                v = rng.standard_normal(X.shape[1])
+                runs = []
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    ON.fast_gauss_window(X, v, sig, 64, 128, 4)
+                    runs.append(time.perf_counter() - t0)
+                ts[h] = statistics.median(runs)
+        n1, n2 = 128 * 128, 512 * 512
+        b = (ts[512] - ts[128]) / (n2 - n1)
+        a = ts[128] - b * n1
+        t_prod = 9 * (a + b * SIDE * SIDE)
+        t_solve = (cfg["mean_iters_plain"] + 2) * t_prod
+        return SIDE * SIDE / t_solve / 1e6, ts
+
+    ncores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    v1, ts1 = med(1)
+    vall, tsall = med(ncores)
+    return {"value": round(vall, 7), "unit": "Mpixel/s", "cores": ncores, "kind": "oracle",
+            "value_1core": round(v1, 7), "cpu": cpu_model(),
+            "sample": "FP64 NFFT oracle (numpy): one window's fast Gauss summation on the central "
+                      "128^2 and 512^2 crops, M=64, n=128, m=4, median of 3 (%.2f s / %.2f s on 1 "
+                      "thread, %.2f s / %.2f s on %d); a + b N fit extrapolated to 9 windows x "
+                      "2048^2 nodes per product and (plain mean iterations + 2) products per solve"
+                      % (ts1[128], ts1[512], tsall[128], tsall[512], ncores)}
 
 
 if __name__ == "__main__":

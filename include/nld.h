@@ -145,7 +145,11 @@ typedef struct {
                      /* entry; a u0 whose initial residual is not finite is replaced by f.  */
                      /* 2: as 1, and u0 is also replaced by f when its initial residual     */
                      /* ||Pi (f - A u0)|| exceeds that of u0 = f (costs one more operator   */
-                     /* application).  Plain PCG from f is the fallback of a warm start.     */
+                     /* application).  3: as 1, and CG starts from b Pi u0 with          */
+                     /* b = <Pi u0, f_perp> / <Pi u0, A Pi u0>, the multiple of the guess    */
+                     /* nearest to the solution in the energy norm (never farther than the   */
+                     /* start u = mean(f) 1; no extra operator application).  Plain PCG from */
+                     /* f is the fallback of a warm start.                                   */
   int32_t precond;   /* 0: none; 1: Jacobi P_a = I + alpha diag(eta); 2: the l2 diagonal   */
                      /* P_b' = (alpha^2 sum_l w_l^2 diag(Gamma_l o Gamma_l 1) + P_a^2)^(1/2) */
                      /* of Sec. 4.3.1 (squared kernels = Gaussians of width sigma_l / sqrt 2, */

@@ -260,7 +260,7 @@ nld_status pcg_solve(nfft_plan_t plan, double alpha, const void* f, void* u,
   if (opts->precond < 0 || opts->precond > 2)
     return fail(NLD_E_INVAL, "pcg_solve: precond must be 0, 1 or 2");
   if (opts->deflate != 0 && opts->deflate != 1) return fail(NLD_E_INVAL, "pcg_solve: deflate must be 0 or 1");
-  if (opts->use_u0 < 0 || opts->use_u0 > 2) return fail(NLD_E_INVAL, "pcg_solve: use_u0 must be 0, 1 or 2");
+  if (opts->use_u0 < 0 || opts->use_u0 > 3) return fail(NLD_E_INVAL, "pcg_solve: use_u0 must be 0, 1, 2 or 3");
   std::memset(info, 0, sizeof(*info));
   info->relres_true = -1.0;
   nld_status result = NLD_OK;
@@ -333,7 +333,7 @@ nld_status adjoint_solve(nfft_plan_t plan, double alpha, const void* f, const vo
   if (opts->precond < 0 || opts->precond > 2)
     return fail(NLD_E_INVAL, "adjoint_solve: precond must be 0, 1 or 2");
   if (opts->deflate != 0 && opts->deflate != 1) return fail(NLD_E_INVAL, "adjoint_solve: deflate must be 0 or 1");
-  if (opts->use_u0 < 0 || opts->use_u0 > 2) return fail(NLD_E_INVAL, "adjoint_solve: use_u0 must be 0, 1 or 2");
+  if (opts->use_u0 < 0 || opts->use_u0 > 3) return fail(NLD_E_INVAL, "adjoint_solve: use_u0 must be 0, 1, 2 or 3");
   std::memset(info, 0, sizeof(*info));
   info->relres_true = -1.0;
   nld_status result = NLD_OK;

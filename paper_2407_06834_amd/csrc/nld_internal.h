@@ -123,6 +123,7 @@ struct CgState {
   double last_pq, last_rho;  // last <p, A p> and <r, s> (diagnostics)
   double sum_pinv;     // sum_i 1 / P_i
   double w2sum;        // sum_l w_l^2 (self terms of D2)
+  double scale_b;      // energy-optimal multiple of a warm start (use_u0 = 3)
   int iters, maxit, done, status, precond, deflate;
   unsigned int ticket[8];
 };

@@ -210,6 +210,51 @@ __global__ void k_cg_direction(const ImgDev* __restrict__ imgs, int first) {
   }
 }
 
+// Energy-optimal multiple of a warm start: with z = Pi u0 and r = f_perp - A z (the initial
+// residual just formed), <z, A z> = <z, f_perp> - <z, r>, and b = <z, f_perp> / <z, A z>
+// minimises ||b z - z*||_A over b (A z* = f_perp), so the scaled start is never farther from
+// the solution in the energy norm than the zero start u = mean(f) 1.  b = 0 when <z, A z> is not
+// positive and finite (a constant guess).
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_cg_scale_sums(const ImgDev* __restrict__ imgs) {
+  const ImgDev& im = imgs[blockIdx.y];
+  CgState* st = im.st;
+  if (st->done || blockIdx.x >= (unsigned)im.nred) return;
+  const T* z = reinterpret_cast<const T*>(im.vec[V_Z]);
+  const T* r = reinterpret_cast<const T*>(im.vec[V_R]);
+  const T* f = reinterpret_cast<const T*>(im.vec[V_F]);
+  const double mf = st->mean_f;
+  double s[2] = {0.0, 0.0};
+  for (long long i = blockIdx.x * (long long)kRedThreads + threadIdx.x; i < im.N;
+       i += (long long)im.nred * kRedThreads) {
+    const double zi = (double)z[i];
+    s[0] += zi * ((double)f[i] - mf);
+    s[1] += zi * (double)r[i];
+  }
+  double tot[2];
+  if (!grid_reduce<2>(s, im.red, &st->ticket[4], tot, im.nred)) return;
+  if (threadIdx.x != 0) return;
+  const double zaz = tot[0] - tot[1];
+  st->scale_b = (zaz > 0.0 && isfinite(zaz) && isfinite(tot[0])) ? tot[0] / zaz : 0.0;
+}
+
+// z <- b z, r <- f_perp - A (b z) = (1 - b) f_perp + b r
+template <typename T>
+__global__ void k_cg_scale_apply(const ImgDev* __restrict__ imgs) {
+  const ImgDev& im = imgs[blockIdx.y];
+  const CgState* st = im.st;
+  if (st->done) return;
+  T* __restrict__ z = reinterpret_cast<T*>(im.vec[V_Z]);
+  T* __restrict__ r = reinterpret_cast<T*>(im.vec[V_R]);
+  const T* __restrict__ f = reinterpret_cast<const T*>(im.vec[V_F]);
+  const double b = st->scale_b, mf = st->mean_f;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < im.N;
+       i += (long long)gridDim.x * blockDim.x) {
+    z[i] = (T)(b * (double)z[i]);
+    r[i] = (T)((1.0 - b) * ((double)f[i] - mf) + b * (double)r[i]);
+  }
+}
+
 template <typename T>
 __global__ void k_cg_finish(const ImgDev* __restrict__ imgs) {
   const ImgDev& im = imgs[blockIdx.y];
@@ -304,8 +349,8 @@ nld_status run_pcg_t(Plan& P, double alpha, const void* f, void* u, const nld_pc
     init_from(V_F, false);
   } else {
     // warm start with plain PCG as the fallback: a guess whose initial residual is not finite
-    // (use_u0 = 1), or also exceeds the residual of the plain start u0 = f (use_u0 = 2), is
-    // replaced by f
+    // (use_u0 = 1, 3), or also exceeds the residual of the plain start u0 = f (use_u0 = 2), is
+    // replaced by f; use_u0 = 3 starts from the energy-optimal multiple of the guess
     double rr_f = INFINITY;
     bool plain_done = false;
     if (o.use_u0 == 2) {
@@ -322,6 +367,15 @@ nld_status run_pcg_t(Plan& P, double alpha, const void* f, void* u, const nld_pc
       if (bad) {
         info.u0_rejected = 1;
         init_from(V_F, true);
+      } else if (o.use_u0 == 3) {
+        // start from the energy-optimal multiple of the guess, then the residual sums again
+        h->done = 0;
+        h->status = NLD_OK;
+        NLD_HIP(hipMemcpyAsync(P.st, h, sizeof(CgState), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_cg_scale_sums<T>, rb, dim3(kRedThreads), 0, s, im);
+        hipLaunchKernelGGL(k_cg_scale_apply<T>, gb, dim3(256), 0, s, im);
+        hipLaunchKernelGGL(k_cg_init2<T>, rb, dim3(kRedThreads), 0, s, im);
+        NLD_HIP(hipGetLastError());
       }
     }
   }

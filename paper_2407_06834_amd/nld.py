@@ -253,11 +253,12 @@ class Plan:
                   u0_guard: str = "finite"):
         """Solve (I + alpha L~) u = f.  Returns (u, info dict).  With a warm start u0,
         u0_guard "finite" falls back to u0 = f when u0's initial residual is not finite,
-        "residual" also when it exceeds the residual of u0 = f (one more product)."""
+        "residual" also when it exceeds the residual of u0 = f (one more product), "scaled"
+        starts from the energy-optimal multiple of u0 - mean(u0) (see use_u0 in nld.h)."""
         u = torch.empty_like(f) if out is None else out
         if u0 is not None:
             u.copy_(u0)
-        mode = 0 if u0 is None else {"finite": 1, "residual": 2}[u0_guard]
+        mode = 0 if u0 is None else {"finite": 1, "residual": 2, "scaled": 3}[u0_guard]
         opts = PcgOpts(float(tol), int(maxit), mode, _precond(precond),
                        int(bool(deflate)), int(bool(true_residual)), int(bool(timing)))
         info = PcgInfo()

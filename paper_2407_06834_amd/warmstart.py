@@ -11,8 +11,10 @@ training on the GPU, evaluation against plain PCG.
    kernels.  cond = (log alpha / 3, (log sigma_l - log 0.1) / 0.7) so every input channel is of
    order one.
 3. Evaluation: seeded 2048 x 2048 images (alpha, sigma_l drawn as in training), one plan per
-   image, PCG from u0 = f (plain) and from u0 = net output (warm), both to relative residual
-   1e-6 against ||f_perp||.  Throughput counts plan, degree vector, network and PCG.
+   image, PCG from u0 = f (plain) and from the energy-optimal multiple of the network output
+   (warm, use_u0 = 3 of pcg_solve), both to relative residual 1e-6 against ||f_perp||; the zero
+   start u = mean(f) 1 (no network) is run beside as a control.  Throughput counts plan,
+   degree vector, network and PCG.
 
     python -m paper_2407_06834_amd.warmstart [--train 2000] [--eval 32] [--eval-side 2048]
 """
@@ -125,14 +127,24 @@ def evaluate(net: WarmStartNet, seeds, side=2048, tol=1e-6, log=None):
         torch.cuda.synchronize()
         t_net = time.perf_counter() - t0
         t0 = time.perf_counter()
-        u_warm, i_warm = plan.pcg_solve(p["alpha"], fv, u0=u0.reshape(-1), tol=tol, maxit=1000)
+        u_warm, i_warm = plan.pcg_solve(p["alpha"], fv, u0=u0.reshape(-1), tol=tol, maxit=1000,
+                                        u0_guard="scaled")
         torch.cuda.synchronize()
         t_warm = time.perf_counter() - t0
+        # control: the zero start u = mean(f) 1 (no network)
+        t0 = time.perf_counter()
+        _, i_zero = plan.pcg_solve(p["alpha"], fv, u0=torch.full_like(fv, float(fv.mean())),
+                                   tol=tol, maxit=1000)
+        torch.cuda.synchronize()
+        t_zero = time.perf_counter() - t0
         plan.close()
         fperp = float(torch.linalg.vector_norm(fv.double() - fv.double().mean()))
         row = dict(seed=s, alpha=p["alpha"], iters_plain=i_plain["iters"], iters_warm=i_warm["iters"],
-                   ms_plan=t_plan * 1e3, ms_plain=t_plain * 1e3, ms_net=t_net * 1e3,
-                   ms_warm=t_warm * 1e3, status=(i_plain["status"], i_warm["status"]),
+                   iters_zero=i_zero["iters"], ms_plan=t_plan * 1e3, ms_plain=t_plain * 1e3,
+                   ms_net=t_net * 1e3, ms_warm=t_warm * 1e3, ms_zero=t_zero * 1e3,
+                   u0_rejected=i_warm["u0_rejected"],
+                   status=(i_plain["status"], i_warm["status"], i_zero["status"]),
+                   zero_start_err_rel=float(torch.linalg.vector_norm(u_plain.double() - fv.double().mean())) / fperp,
                    diff_rel=float(torch.linalg.vector_norm((u_warm - u_plain).double())) / fperp,
                    u0_err_rel=float(torch.linalg.vector_norm((u0.reshape(-1) - u_plain).double())) / fperp)
         rows.append(row)
@@ -141,10 +153,14 @@ def evaluate(net: WarmStartNet, seeds, side=2048, tol=1e-6, log=None):
     n_px = side * side * len(rows)
     t_p = sum(r["ms_plan"] + r["ms_plain"] for r in rows) / 1e3
     t_w = sum(r["ms_plan"] + r["ms_net"] + r["ms_warm"] for r in rows) / 1e3
+    t_z = sum(r["ms_plan"] + r["ms_zero"] for r in rows) / 1e3
     return dict(images=len(rows), side=side,
                 iters_plain=float(np.mean([r["iters_plain"] for r in rows])),
                 iters_warm=float(np.mean([r["iters_warm"] for r in rows])),
+                iters_zero=float(np.mean([r["iters_zero"] for r in rows])),
                 mpix_plain=n_px / t_p / 1e6, mpix_warm=n_px / t_w / 1e6, speedup=t_p / t_w,
+                mpix_zero=n_px / t_z / 1e6,
+                zero_start_err_rel_max=max(r["zero_start_err_rel"] for r in rows),
                 ms_net_mean=float(np.mean([r["ms_net"] for r in rows])),
                 max_diff_rel=max(r["diff_rel"] for r in rows),
                 u0_err_rel_mean=float(np.mean([r["u0_err_rel"] for r in rows])))

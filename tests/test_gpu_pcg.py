@@ -203,3 +203,27 @@ def test_worse_warm_start_falls_back_only_with_the_residual_guard():
     assert info2["iters"] == i_plain["iters"] and torch.equal(u2, u_plain)
     assert info3["status"] == "OK" and not info3["u0_rejected"] and info3["iters"] <= 1
     assert rel(u1.cpu().numpy(), u_plain.cpu().numpy()) < 1e-8
+
+
+def test_energy_scaled_warm_start():
+    # use_u0 = 3: the start b Pi u0 with the energy-optimal b.  From the solution itself b = 1 and
+    # CG stops at once; from a random guess b is tiny and CG needs no more iterations than from
+    # the zero start u = mean(f) 1 (+1 for rounding); a NaN guess falls back to u0 = f.
+    torch, nld, f, img, F, wins, wts, plan = _problem(32, 32, 1, 9, torch_gpu().float64,
+                                                      [0.1] * 4, 64, 6)
+    fv = img.reshape(-1)
+    u_plain, i_plain = plan.pcg_solve(2.0, fv, tol=1e-10)
+    mean_start = torch.full_like(fv, float(fv.mean()))
+    _, i_zero = plan.pcg_solve(2.0, fv, u0=mean_start, tol=1e-10)
+    u1, i1 = plan.pcg_solve(2.0, fv, u0=u_plain, tol=1e-9, u0_guard="scaled")
+    g = torch.Generator(device="cpu").manual_seed(4)
+    rnd = torch.randn(fv.shape, generator=g, dtype=fv.dtype).to(fv.device)
+    u2, i2 = plan.pcg_solve(2.0, fv, u0=rnd, tol=1e-10, u0_guard="scaled")
+    bad = fv.clone()
+    bad[3] = float("inf")
+    u3, i3 = plan.pcg_solve(2.0, fv, u0=bad, tol=1e-10, u0_guard="scaled")
+    plan.close()
+    assert i1["status"] == "OK" and i1["iters"] <= 1 and not i1["u0_rejected"]
+    assert i2["status"] == "OK" and i2["iters"] <= i_zero["iters"] + 1
+    assert rel(u2.cpu().numpy(), u_plain.cpu().numpy()) < 1e-8
+    assert i3["status"] == "OK" and i3["u0_rejected"] and torch.equal(u3, u_plain)
