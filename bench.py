@@ -1,8 +1,9 @@
 """Benchmark: learned warm start vs plain deflated PCG on 2048 x 2048 synthetic images, one MI355X.
 
-One step = one 2048 x 2048 evaluation image (seeded: 20 rectangles, 12 discs, noise 0.1; alpha
-~ logU[0.05, 20] and sigma_l ~ U[0.05, 0.2] per window, drawn per image) through the whole hot
-path three times:
+One step = one 2048 x 2048 evaluation image (seeded: 20 rectangles, 12 discs, noise 0.1;
+sigma_l ~ U[0.05, 0.2] per window and a smoothing strength s ~ logU[0.3, 30] drawn per image,
+alpha = s / mean(eta) with eta the plan's zero-diagonal degree; --alpha-rule absolute draws
+alpha ~ logU[0.05, 20] instead) through the whole hot path three times:
   plain  features (5x5 patch + position, 27 dims), plan over 9 windows of 3 (torus scaling, tile
          sort, Fourier multipliers, bandwidth per window for a 1e-4 product, m = 4, FP32 with
          FP64 reductions) and degree vector, then deflated Jacobi PCG from u0 = f to relative
@@ -49,8 +50,10 @@ WEIGHTS = os.path.join(ROOT, "paper_2407_06834_amd", "weights", "warmstart_c5.np
 # HBM bytes per product from the rocprofv3 counter runs in profiles/ (valid for the kernel
 # sources of the recorded hash)
 TRAFFIC = {
-    "c2_512": {"sha1": "6418c9213667ee5024d0887cd5988a2525a911c2", "bytes": 834913906},
-    "c5_2048": {"sha1": None, "bytes": None},
+    # the 512^2 section of the default command
+    "c2_512": {"sha1": "4bae89d2f993e37cdb2f31f894ed491e205037e9", "bytes": 816896000},
+    # the timed images of the default command (seeds 301..304, --steps 4 --warmup 1)
+    "c5_2048": {"sha1": "4bae89d2f993e37cdb2f31f894ed491e205037e9", "bytes": 10532220928},
 }
 KERNEL_SOURCES = ("paper_2407_06834_amd/csrc/nfft.hip", "paper_2407_06834_amd/csrc/plan.hip",
                   "paper_2407_06834_amd/csrc/nld_internal.h", "paper_2407_06834_amd/csrc/nld_device.h")
@@ -103,6 +106,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c2", action="store_true")
     ap.add_argument("--profile-copy", action="store_true")
+    ap.add_argument("--alpha-rule", choices=("strength", "absolute"), default="strength",
+                    help="strength: alpha = s / mean(eta), s ~ logU[0.3, 30] (default); "
+                         "absolute: alpha ~ logU[0.05, 20]")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -115,7 +121,8 @@ def main():
 
     from paper_2407_06834_amd import nld
     from paper_2407_06834_amd.cnn import WarmStartNet
-    from paper_2407_06834_amd.warmstart import cond_of, draw_problem
+    from paper_2407_06834_amd import warmstart as WS
+    from paper_2407_06834_amd.warmstart import cond_of, draw_problem, problem_alpha
 
     nld.load()
     if not os.path.exists(args.weights):
@@ -131,7 +138,8 @@ def main():
     total = args.warmup + args.steps
     probs = [draw_problem(EVAL_SEED0 + k, side=SIDE, noise=0.1) for k in range(total)]
     imgs = [torch.tensor(p["f"], dtype=torch.float32, device="cuda") for p in probs]
-    conds = [np.array([cond_of(p["alpha"], p["sigma"])]) for p in probs]
+    WS.set_alpha_rule(args.alpha_rule)
+    conds = [np.array([cond_of(p)]) for p in probs]
     torch.cuda.synchronize()
 
     def step(k, rec):
@@ -141,21 +149,21 @@ def main():
         t0 = time.perf_counter()
         F = nld.features_from_image(img, RHO)
         plan = nld.Plan(F, wins, p["sigma"], [1.0] * L, cutoff=4, matvec_tol=1e-4)
-        plan.degree_vector()
+        alpha = problem_alpha(p, plan.degree_vector(), float(L))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        _, ip = plan.pcg_solve(p["alpha"], fv, tol=TOL, maxit=1000, timing=rec is not None)
+        _, ip = plan.pcg_solve(alpha, fv, tol=TOL, maxit=1000, timing=rec is not None)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         u0 = net.predict(img.reshape(1, SIDE, SIDE), conds[k]).reshape(-1)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
-        _, iw = plan.pcg_solve(p["alpha"], fv, u0=u0, tol=TOL, maxit=1000,
+        _, iw = plan.pcg_solve(alpha, fv, u0=u0, tol=TOL, maxit=1000,
                                timing=rec is not None, u0_guard="scaled")
         torch.cuda.synchronize()
         t4 = time.perf_counter()
         # control without the network: the zero start u = mean(f) 1
-        _, iz = plan.pcg_solve(p["alpha"], fv, u0=torch.full_like(fv, float(fv.mean())), tol=TOL,
+        _, iz = plan.pcg_solve(alpha, fv, u0=torch.full_like(fv, float(fv.mean())), tol=TOL,
                                maxit=1000)
         torch.cuda.synchronize()
         t5 = time.perf_counter()
@@ -163,7 +171,7 @@ def main():
         plan.close()
         if rec is not None:
             rec.append(dict(plan=t1 - t0, plain=t2 - t1, net=t3 - t2, warm=t4 - t3, zero=t5 - t4,
-                            ip=ip, iw=iw, iz=iz, grids=grids))
+                            ip=ip, iw=iw, iz=iz, grids=grids, alpha=alpha))
 
     for k in range(args.warmup):
         step(k, None)
@@ -210,11 +218,14 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "2048x2048 synthetic images (20 rectangles, 12 discs, noise 0.1; seeds "
-                        "%d..%d), alpha ~ logU[0.05,20], sigma_l ~ U[0.05,0.2], 5x5 patch + "
+                        "%d..%d), %s, sigma_l ~ U[0.05,0.2], 5x5 patch + "
                         "position in 9 windows of 3, FP32 NFFT (m=4, bandwidth per window for a "
                         "1e-4 product) with FP64 reductions, deflated Jacobi PCG to 1e-6; warm "
                         "start from the 5-layer BF16 network vs plain PCG from u0=f"
-                        % (EVAL_SEED0 + args.warmup, EVAL_SEED0 + total - 1),
+                        % (EVAL_SEED0 + args.warmup, EVAL_SEED0 + total - 1,
+                           "alpha = s / mean(eta), s ~ logU[0.3,30]" if args.alpha_rule ==
+                           "strength" else "alpha ~ logU[0.05,20]"),
+            "alpha_mean": round(float(np.mean([r["alpha"] for r in recs])), 8),
             "value_is": "warm-start path: plan + degree + network + PCG",
             "mpix_warm": round(mpix_warm, 4),
             "mpix_plain": round(mpix_plain, 4),
@@ -238,7 +249,9 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(nf / (ms * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4) if ms > 0 else 0.0,
-            "traffic": (round(tr["bytes"] / 1e9, 4) if tr["sha1"] == sha and tr["bytes"] else None),
+            "traffic": (round(tr["bytes"] / 1e9, 4) if tr["sha1"] == sha and tr["bytes"] and
+                        (args.steps, args.warmup) == (4, 1) and args.alpha_rule == "strength"
+                        else None),
             "traffic_unit": "GB per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "flops_per_launch": round(nf / max(1, n_prod)),
             "bytes_per_launch": round(nb / max(1, n_prod)),

@@ -36,18 +36,51 @@ TRAIN_SIDES = (256, 384, 512, 768, 1024)
 RHO = 2
 
 
+# How alpha is drawn.  "strength": the smoothing strength s = alpha * mean(eta) is drawn
+# log-uniformly in [0.3, 30] and alpha = s / mean(eta) with eta the plan's zero-diagonal degree,
+# so that images of every size are denoised to a similar degree.  "absolute": alpha itself is
+# drawn log-uniformly in [0.05, 20]; with unit window weights the degree grows with the number
+# of pixels (the patch windows have no position, every pixel of similar patch is a neighbour),
+# and at 2048 x 2048 the solution is then the constant image mean(f) 1 to within 1e-4 of
+# ||f - mean f||, whatever the network predicts.
+ALPHA_RULE = "strength"
+ABS_RANGE = (0.05, 20.0)
+STRENGTH_RANGE = (0.3, 30.0)
+
+
 def draw_problem(seed: int, side: int | None = None, sides=TRAIN_SIDES, noise=None):
     rng = np.random.default_rng(seed)
     s = int(rng.choice(sides)) if side is None else side
     nz = float(rng.uniform(0.05, 0.2)) if noise is None else noise
-    alpha = float(np.exp(rng.uniform(np.log(0.05), np.log(20.0))))
+    alpha = float(np.exp(rng.uniform(np.log(ABS_RANGE[0]), np.log(ABS_RANGE[1]))))
     sigma = [float(x) for x in rng.uniform(0.05, 0.2, 9)]
+    # the same uniform draw placed in the strength range
+    t = (math.log(alpha) - math.log(ABS_RANGE[0])) / math.log(ABS_RANGE[1] / ABS_RANGE[0])
+    strength = math.exp(math.log(STRENGTH_RANGE[0]) + t * math.log(STRENGTH_RANGE[1] /
+                                                                    STRENGTH_RANGE[0]))
     uc, f = make_image(seed, s, s, 20, 12, nz)
-    return dict(side=s, alpha=alpha, sigma=sigma, f=f, seed=seed)
+    return dict(side=s, alpha=alpha, strength=strength, sigma=sigma, f=f, seed=seed)
 
 
-def cond_of(alpha, sigma):
-    return [math.log(alpha) / 3.0] + [(math.log(s) - math.log(0.1)) / 0.7 for s in sigma]
+def set_alpha_rule(rule: str):
+    global ALPHA_RULE
+    if rule not in ("strength", "absolute"):
+        raise ValueError(rule)
+    ALPHA_RULE = rule
+
+
+def problem_alpha(p, D: torch.Tensor, wsum: float) -> float:
+    """alpha of problem p under ALPHA_RULE; D is the plan's degree vector (FP64, device)."""
+    if ALPHA_RULE == "absolute":
+        return p["alpha"]
+    return p["strength"] / (float(D.mean()) - wsum)
+
+
+def cond_of(p):
+    """Network conditioning: log of the drawn alpha (absolute rule) or strength, and the
+    windows' log widths, each scaled to order one."""
+    x = p["alpha"] if ALPHA_RULE == "absolute" else p["strength"]
+    return [math.log(x) / 3.0] + [(math.log(s) - math.log(0.1)) / 0.7 for s in p["sigma"]]
 
 
 def generate(seeds, sides=TRAIN_SIDES, batch=16, tol=1e-6, log=None):
@@ -59,21 +92,21 @@ def generate(seeds, sides=TRAIN_SIDES, batch=16, tol=1e-6, log=None):
     out = []
     for b0 in range(0, len(probs), batch):
         chunk = probs[b0:b0 + batch]
-        plans, fs = [], []
+        plans, fs, alphas = [], [], []
         for p in chunk:
             img = torch.tensor(p["f"], dtype=torch.float32, device="cuda")
             F = nld.features_from_image(img, RHO)
-            plans.append(nld.Plan(F, wins, p["sigma"], [1.0] * 9, cutoff=4, matvec_tol=1e-4))
+            plan = nld.Plan(F, wins, p["sigma"], [1.0] * 9, cutoff=4, matvec_tol=1e-4)
+            alphas.append(problem_alpha(p, plan.degree_vector(), 9.0))
+            plans.append(plan)
             fs.append(img.reshape(-1))
-        us, infos, st = nld.pcg_solve_batched(plans, [p["alpha"] for p in chunk], fs, tol=tol,
-                                              maxit=1000)
+        us, infos, st = nld.pcg_solve_batched(plans, alphas, fs, tol=tol, maxit=1000)
         for p, f, u, i, pl in zip(chunk, fs, us, infos, plans):
             pl.close()
             if i["status"] != "OK":
                 continue
             n = p["side"]
-            out.append(dict(f=f.reshape(n, n), u=u.reshape(n, n), side=n,
-                            cond=cond_of(p["alpha"], p["sigma"])))
+            out.append(dict(f=f.reshape(n, n), u=u.reshape(n, n), side=n, cond=cond_of(p)))
         if log:
             log({"generated": len(out), "of": len(probs)})
     return out
@@ -115,31 +148,31 @@ def evaluate(net: WarmStartNet, seeds, side=2048, tol=1e-6, log=None):
         t0 = time.perf_counter()
         F = nld.features_from_image(img, RHO)
         plan = nld.Plan(F, wins, p["sigma"], [1.0] * 9, cutoff=4, matvec_tol=1e-4)
-        plan.degree_vector()
+        alpha = problem_alpha(p, plan.degree_vector(), 9.0)
         torch.cuda.synchronize()
         t_plan = time.perf_counter() - t0
         t0 = time.perf_counter()
-        u_plain, i_plain = plan.pcg_solve(p["alpha"], fv, tol=tol, maxit=1000)
+        u_plain, i_plain = plan.pcg_solve(alpha, fv, tol=tol, maxit=1000)
         torch.cuda.synchronize()
         t_plain = time.perf_counter() - t0
         t0 = time.perf_counter()
-        u0 = net.predict(img.reshape(1, side, side), np.array([cond_of(p["alpha"], p["sigma"])]))
+        u0 = net.predict(img.reshape(1, side, side), np.array([cond_of(p)]))
         torch.cuda.synchronize()
         t_net = time.perf_counter() - t0
         t0 = time.perf_counter()
-        u_warm, i_warm = plan.pcg_solve(p["alpha"], fv, u0=u0.reshape(-1), tol=tol, maxit=1000,
+        u_warm, i_warm = plan.pcg_solve(alpha, fv, u0=u0.reshape(-1), tol=tol, maxit=1000,
                                         u0_guard="scaled")
         torch.cuda.synchronize()
         t_warm = time.perf_counter() - t0
         # control: the zero start u = mean(f) 1 (no network)
         t0 = time.perf_counter()
-        _, i_zero = plan.pcg_solve(p["alpha"], fv, u0=torch.full_like(fv, float(fv.mean())),
+        _, i_zero = plan.pcg_solve(alpha, fv, u0=torch.full_like(fv, float(fv.mean())),
                                    tol=tol, maxit=1000)
         torch.cuda.synchronize()
         t_zero = time.perf_counter() - t0
         plan.close()
         fperp = float(torch.linalg.vector_norm(fv.double() - fv.double().mean()))
-        row = dict(seed=s, alpha=p["alpha"], iters_plain=i_plain["iters"], iters_warm=i_warm["iters"],
+        row = dict(seed=s, alpha=alpha, iters_plain=i_plain["iters"], iters_warm=i_warm["iters"],
                    iters_zero=i_zero["iters"], ms_plan=t_plan * 1e3, ms_plain=t_plain * 1e3,
                    ms_net=t_net * 1e3, ms_warm=t_warm * 1e3, ms_zero=t_zero * 1e3,
                    u0_rejected=i_warm["u0_rejected"],
@@ -173,7 +206,9 @@ def main():
     ap.add_argument("--eval", type=int, default=32)
     ap.add_argument("--eval-side", type=int, default=2048)
     ap.add_argument("--save", default="")
+    ap.add_argument("--alpha-rule", choices=("strength", "absolute"), default=ALPHA_RULE)
     args = ap.parse_args()
+    set_alpha_rule(args.alpha_rule)
     nld.load()
 
     def log(rec):
