@@ -5,8 +5,8 @@ sigma_l ~ U[0.05, 0.2] per window and a smoothing strength s ~ logU[0.3, 30] dra
 alpha = s / mean(eta) with eta the plan's zero-diagonal degree; --alpha-rule absolute draws
 alpha ~ logU[0.05, 20] instead) through the whole hot path three times:
   plain  features (5x5 patch + position, 27 dims), plan over 9 windows of 3 (torus scaling, tile
-         sort, Fourier multipliers, bandwidth per window for a 1e-4 product, m = 4, FP32 with
-         FP64 reductions) and degree vector, then deflated Jacobi PCG from u0 = f to relative
+         sort, Fourier multipliers, bandwidth per window for a 1e-4 product, m = 4, grids of at
+         most 128 points per dimension, FP32 with FP64 reductions) and degree vector, then deflated Jacobi PCG from u0 = f to relative
          residual 1e-6;
   warm   the same features, plan and degree vector, the warm-start network (BF16 MFMA kernels)
          predicting u0 from (f, alpha, sigma_l), then the same PCG from the energy-optimal
@@ -46,14 +46,16 @@ RHO = 2
 TOL = 1e-6
 EVAL_SEED0 = 300
 WEIGHTS = os.path.join(ROOT, "paper_2407_06834_amd", "weights", "warmstart_c5.npy")
+# grids are capped at 128 points per dimension (windows with M = 96 oversample by 4/3)
+MAX_GRID = 128
 
 # HBM bytes per product from the rocprofv3 counter runs in profiles/ (valid for the kernel
 # sources of the recorded hash)
 TRAFFIC = {
     # the 512^2 section of the default command
-    "c2_512": {"sha1": "4bae89d2f993e37cdb2f31f894ed491e205037e9", "bytes": 816896000},
+    "c2_512": {"sha1": "5d80cbfae80490b61438358bf09d12ea3cbbcf1e", "bytes": 816886682},
     # the timed images of the default command (seeds 301..304, --steps 4 --warmup 1)
-    "c5_2048": {"sha1": "4bae89d2f993e37cdb2f31f894ed491e205037e9", "bytes": 10532220928},
+    "c5_2048": {"sha1": "5d80cbfae80490b61438358bf09d12ea3cbbcf1e", "bytes": 9018729472},
 }
 KERNEL_SOURCES = ("paper_2407_06834_amd/csrc/nfft.hip", "paper_2407_06834_amd/csrc/plan.hip",
                   "paper_2407_06834_amd/csrc/nld_internal.h", "paper_2407_06834_amd/csrc/nld_device.h")
@@ -148,7 +150,8 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F = nld.features_from_image(img, RHO)
-        plan = nld.Plan(F, wins, p["sigma"], [1.0] * L, cutoff=4, matvec_tol=1e-4)
+        plan = nld.Plan(F, wins, p["sigma"], [1.0] * L, cutoff=4, matvec_tol=1e-4,
+                        max_grid=MAX_GRID)
         alpha = problem_alpha(p, plan.degree_vector(), float(L))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -220,7 +223,8 @@ def main():
             "workload": "2048x2048 synthetic images (20 rectangles, 12 discs, noise 0.1; seeds "
                         "%d..%d), %s, sigma_l ~ U[0.05,0.2], 5x5 patch + "
                         "position in 9 windows of 3, FP32 NFFT (m=4, bandwidth per window for a "
-                        "1e-4 product) with FP64 reductions, deflated Jacobi PCG to 1e-6; warm "
+                        "1e-4 product, grids of at most 128^3) with FP64 reductions, deflated "
+                        "Jacobi PCG to 1e-6; warm "
                         "start from the 5-layer BF16 network vs plain PCG from u0=f"
                         % (EVAL_SEED0 + args.warmup, EVAL_SEED0 + total - 1,
                            "alpha = s / mean(eta), s ~ logU[0.3,30]" if args.alpha_rule ==

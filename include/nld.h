@@ -66,6 +66,11 @@ typedef enum { NLD_FP32 = 0, NLD_FP64 = 1 } nld_prec;
  *   tile        grid tile extent of 3-dimensional windows for the spreading and gathering
  *               schedules: 8 or 16 (0 selects 8).  Results do not depend on it beyond
  *               rounding; it trades halo work against workgroup count.
+ *   max_grid    largest grid side n (0 for no limit, else 32, 64, 128 or 256): a window whose
+ *               oversampled grid would exceed it uses n = max_grid instead, provided that still
+ *               oversamples its band by at least 1.25 (n >= 1.25 M); the window function's
+ *               shape follows the ratio n / M, so the same cutoff stays accurate (about 1e-6
+ *               relative at m = 4 for n / M = 4/3, against 1e-7 at n / M = 2).
  */
 typedef struct {
   int32_t n_windows;
@@ -80,6 +85,7 @@ typedef struct {
   double matvec_tol;
   nld_prec prec;
   int32_t tile;
+  int32_t max_grid;
 } nld_kernel_desc;
 
 /* Per-window parameters chosen by the plan (for reports and tests). */

@@ -126,6 +126,9 @@ nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t 
       if (!bw_ok(desc->win_bandwidth[l]))
         return fail(NLD_E_INVAL, "nfft_plan: window bandwidth must be 0 or even in [8, 256]");
   if (desc->cutoff < 0 || desc->cutoff > 8) return fail(NLD_E_INVAL, "nfft_plan: cutoff must be in [0, 8]");
+  if (desc->max_grid != 0 && desc->max_grid != 32 && desc->max_grid != 64 &&
+      desc->max_grid != 128 && desc->max_grid != 256)
+    return fail(NLD_E_INVAL, "nfft_plan: max_grid must be 0, 32, 64, 128 or 256");
   const double os = desc->oversampling == 0.0 ? 2.0 : desc->oversampling;
   if (!std::isfinite(os) || os < 1.25 || os > 8.0)
     return fail(NLD_E_INVAL, "nfft_plan: oversampling must be in [1.25, 8]");
@@ -154,6 +157,7 @@ nld_status nfft_plan(nfft_plan_t* out, const void* features, int64_t N, int32_t 
     P.oversampling = os;
     P.tol = tol;
     P.tile3 = desc->tile;
+    P.max_grid = desc->max_grid;
     P.st_host = (nld::CgState*)nld::pinned_get(sizeof(nld::CgState));
     int dev = 0, lds = 65536;
     NLD_HIP(hipGetDevice(&dev));

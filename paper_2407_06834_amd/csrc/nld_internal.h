@@ -259,6 +259,7 @@ struct Plan {
   ConvJob* d_conv_u[3] = {nullptr, nullptr, nullptr};
   int conv_begin_u[3][5] = {{0}};
   int tile3 = 0;                   // requested tile extent of 3-D windows (0: default)
+  int max_grid = 0;                // largest grid side (0: no limit beyond 256)
 };
 
 // ------------------------------------------------------------------ launchers

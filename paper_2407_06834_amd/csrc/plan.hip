@@ -692,6 +692,8 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     int n = next_pow2((int)std::ceil(P.oversampling * M - 1e-9));
     n = std::max(n, 32);
     if (n <= M) n = next_pow2(M + 1);
+    // a grid cap: the largest allowed grid if it still oversamples the band by 1.25
+    if (P.max_grid > 0 && n > P.max_grid && 4 * P.max_grid >= 5 * M) n = P.max_grid;
     if (n > 256) throw std::invalid_argument("grid larger than 256 points per dimension");
     if (2 * m > n / 2) throw std::invalid_argument("cutoff too large for the grid");
     const double b = M_PI * (2.0 - (double)M / n);

@@ -35,7 +35,8 @@ class KernelDesc(ctypes.Structure):
                 ("weight", ctypes.POINTER(ctypes.c_double)), ("bandwidth", ctypes.c_int32),
                 ("win_bandwidth", ctypes.POINTER(ctypes.c_int32)), ("cutoff", ctypes.c_int32),
                 ("oversampling", ctypes.c_double), ("matvec_tol", ctypes.c_double),
-                ("prec", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("max_grid", ctypes.c_int32)]
 
 
 class WindowInfo(ctypes.Structure):
@@ -173,7 +174,7 @@ class Plan:
 
     def __init__(self, features: torch.Tensor, windows, sigma, weight, bandwidth: int = 0,
                  cutoff: int = 0, oversampling: float = 2.0, matvec_tol: float = 1e-6,
-                 win_bandwidth=None, tile: int = 0, stream=None):
+                 win_bandwidth=None, tile: int = 0, max_grid: int = 0, stream=None):
         lib = load()
         if features.dim() != 2 or not features.is_cuda:
             raise ValueError("features: expected a (d, N) CUDA tensor")
@@ -193,7 +194,8 @@ class Plan:
         self._wbw = (ctypes.c_int32 * L)(*win_bandwidth) if win_bandwidth is not None else None
         desc = KernelDesc(L, self._wd, self._wf, self._sig, self._wt, int(bandwidth),
                           self._wbw if self._wbw is not None else None, int(cutoff),
-                          float(oversampling), float(matvec_tol), self.prec, int(tile))
+                          float(oversampling), float(matvec_tol), self.prec, int(tile),
+                          int(max_grid))
         h = ctypes.c_void_p()
         _check(lib.nfft_plan(ctypes.byref(h), ctypes.c_void_p(self.features.data_ptr()), self.N,
                              self.d, ctypes.byref(desc), _stream(stream)))

@@ -33,6 +33,8 @@ from .cnn import WarmStartNet
 from .synth import make_image
 
 TRAIN_SIDES = (256, 384, 512, 768, 1024)
+# grids are capped at 128 points per dimension (windows with M = 96 oversample by 4/3)
+MAX_GRID = 128
 RHO = 2
 
 
@@ -96,7 +98,8 @@ def generate(seeds, sides=TRAIN_SIDES, batch=16, tol=1e-6, log=None):
         for p in chunk:
             img = torch.tensor(p["f"], dtype=torch.float32, device="cuda")
             F = nld.features_from_image(img, RHO)
-            plan = nld.Plan(F, wins, p["sigma"], [1.0] * 9, cutoff=4, matvec_tol=1e-4)
+            plan = nld.Plan(F, wins, p["sigma"], [1.0] * 9, cutoff=4, matvec_tol=1e-4,
+                            max_grid=MAX_GRID)
             alphas.append(problem_alpha(p, plan.degree_vector(), 9.0))
             plans.append(plan)
             fs.append(img.reshape(-1))
@@ -147,7 +150,8 @@ def evaluate(net: WarmStartNet, seeds, side=2048, tol=1e-6, log=None):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F = nld.features_from_image(img, RHO)
-        plan = nld.Plan(F, wins, p["sigma"], [1.0] * 9, cutoff=4, matvec_tol=1e-4)
+        plan = nld.Plan(F, wins, p["sigma"], [1.0] * 9, cutoff=4, matvec_tol=1e-4,
+                            max_grid=MAX_GRID)
         alpha = problem_alpha(p, plan.degree_vector(), 9.0)
         torch.cuda.synchronize()
         t_plan = time.perf_counter() - t0

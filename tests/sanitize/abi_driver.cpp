@@ -35,6 +35,8 @@ int main() {
   expect("plan odd bandwidth", nfft_plan(&plan, fake, 100, 3, &bad, nullptr), NLD_E_INVAL);
   bad = d; bad.cutoff = 9;
   expect("plan cutoff", nfft_plan(&plan, fake, 100, 3, &bad, nullptr), NLD_E_INVAL);
+  bad = d; bad.max_grid = 100;
+  expect("plan max_grid", nfft_plan(&plan, fake, 100, 3, &bad, nullptr), NLD_E_INVAL);
   bad = d; bad.n_windows = 0;
   expect("plan no windows", nfft_plan(&plan, fake, 100, 3, &bad, nullptr), NLD_E_INVAL);
   double sneg[2] = {-1.0, 0.1};

@@ -58,6 +58,7 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert plan(bandwidth=63) == nld.NLD_E_INVAL
     assert plan(cutoff=9) == nld.NLD_E_INVAL
     assert plan(oversampling=1.0) == nld.NLD_E_INVAL
+    assert plan(max_grid=100) == nld.NLD_E_INVAL and "max_grid" in err()
     assert plan(prec=7) == nld.NLD_E_INVAL
     assert plan(tile=12) == nld.NLD_E_INVAL and "tile" in err()
     assert plan(n_windows=0) == nld.NLD_E_INVAL
