@@ -115,6 +115,25 @@ __device__ __forceinline__ double lane_fetch(double v, int byte_addr) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// acc[i] += w(lane i of this lane's row of 16) * b for i < 8: the row broadcast (DPP
+// row_newbcast) is part of each FMA, so no readlane or separate move is issued.  The leading
+// s_nop covers the two wait states a DPP read needs after a VALU write of its source.  Same
+// single-rounding FMA as fmaf(b, w_i, acc[i]).
+__device__ __forceinline__ void fmac_row_bcast8(float (&acc)[8], float w, float b) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %8, %9 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %1, %8, %9 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %2, %8, %9 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %3, %8, %9 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %4, %8, %9 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %5, %8, %9 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %6, %8, %9 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %7, %8, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf"
+      : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]), "+v"(acc[5]),
+        "+v"(acc[6]), "+v"(acc[7])
+      : "v"(w), "v"(b));
+}
+
 // Weights of the W = 2m taps of one node in one dimension (tap i at cell floor(u) - m + 1 + i,
 // distance fr + m - 1 - i): the per-tap window polynomials evaluated at x = 2 fr - 1.
 template <typename T, int W, typename P>
@@ -126,7 +145,7 @@ __device__ __forceinline__ void poly_row(P psi, T fr, T* wt) {
 }
 
 // ---------------------------------------------------------------------------- spreading
-// One workgroup (4 wavefronts) per chunk (<= 2048) of a tile's nodes, which the plan sorted by
+// One workgroup (4 wavefronts) per chunk (<= 4096) of a tile's nodes, which the plan sorted by
 // tile and then by cell, so nodes sharing a grid cell are consecutive ("runs").  A wavefront
 // walks its quarter of the chunk one node at a time; lane l owns the tap pair (i1, i2) of the
 // last two kept dimensions and keeps the 2m taps of the first kept dimension in registers, so a
@@ -208,8 +227,16 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   // [W, 2W) the second's, [2W, 3W) the third's (one polynomial per lane and node); the lane that
   // owns tap pair (i1, i2) of the last two dimensions fetches its two factors with ds_bpermute,
   // and the first dimension's W weights are broadcast to every lane.
+  // FP32, 3 kept dimensions, 8 taps (m = 4): every row of 16 lanes holds the first dimension's
+  // weights in its lanes 0-7 (the row broadcast of fmac_row_bcast8 reads them there); lanes
+  // 8-15 hold the second dimension's in rows 0 and 2 and the third's in rows 1 and 3.  A node's
+  // x = 2 f - 1 per dimension and its scaled value are staged per wavefront in LDS.
+  constexpr bool kDpp = TD == 3 && W == 8 && sizeof(T) == 4;
+  __shared__ float4 s_stage[kDpp ? kSpreadWaves * 64 : 1];
   static_assert(TD * W <= 64, "one lane per tap and dimension");
-  const int my_tap = lane % W, my_dim = lane / W;   // lanes with my_dim >= TD idle here
+  const int my_tap = kDpp ? (lane & 7) : lane % W;
+  const int my_dim = kDpp ? ((lane & 8) ? 1 + ((lane >> 4) & 1) : 0)
+                          : lane / W;               // lanes with my_dim >= TD idle here
   // x = 2 f - 1 of this lane's dimension as three FMAs with per-lane factors 2 or 0 (a node's
   // fractions are wave-uniform scalars): the same rounding as 2 f - 1, no selects
   const T sel0 = my_dim == 0 ? (T)2 : (T)0, sel1 = my_dim == 1 ? (T)2 : (T)0,
@@ -226,8 +253,8 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     const int tt = pv[k] ? t : 0;
     i1[k] = (TD == 1) ? 0 : tt / W;
     i2[k] = (TD == 1) ? tt : tt % W;
-    src2[k] = ((TD - 1) * W + i2[k]) * 4;              // byte addresses of the source lanes
-    src1[k] = (TD >= 2) ? ((TD - 2) * W + i1[k]) * 4 : 0;
+    src2[k] = (kDpp ? 24 + i2[k] : (TD - 1) * W + i2[k]) * 4;   // byte addresses of the source
+    src1[k] = kDpp ? (8 + i1[k]) * 4 : (TD >= 2) ? ((TD - 2) * W + i1[k]) * 4 : 0;   // lanes
   }
   const int o0 = tile_origin(w, job.tile, 0), o1 = tile_origin(w, job.tile, 1),
             o2 = tile_origin(w, job.tile, 2);
@@ -274,6 +301,41 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   const int npts = job.pend - job.pbeg;
   const int per = (npts + kSpreadWaves - 1) / kSpreadWaves;
   const int q0 = job.pbeg + wave * per, q1 = min(job.pend, q0 + per);
+  if constexpr (kDpp) {
+    // the wavefront's own 64 entries of s_stage; LDS operations of one wavefront execute in
+    // order, so the stores are visible to the loads of the node loop below and the next
+    // round's stores follow them
+    float4* stg = s_stage + wave * 64;
+    float (&a8)[8] = accr[0];
+    for (int base_p = q0; base_p < q1; base_p += 64) {
+      const int p = base_p + lane;
+      const bool ok = p < q1;
+      const unsigned mb = ok ? g_base[p] : 0u;
+      float4 nd;
+      nd.x = ok ? fmaf(g_frac[p], 2.0f, -1.0f) : 0.0f;
+      nd.y = ok ? fmaf(g_frac[LN + p], 2.0f, -1.0f) : 0.0f;
+      nd.z = ok ? fmaf(g_frac[2 * LN + p], 2.0f, -1.0f) : 0.0f;
+      nd.w = ok ? v[g_idx[p]] * scale_t : 0.0f;
+      __builtin_amdgcn_wave_barrier();
+      stg[lane] = nd;
+      __builtin_amdgcn_wave_barrier();
+      const LdsPtr<float> sf = (LdsPtr<float>)stg;
+      const int cnt = __builtin_amdgcn_readfirstlane(min(64, q1 - base_p));
+      for (int q = 0; q < cnt; ++q) {
+        const unsigned bq = __builtin_amdgcn_readfirstlane(lane_bcast(mb, q));
+        if (bq != cur) {
+          if (cur != kNone) flush();
+          cur = bq;
+        }
+        const float x = sf[4 * q + my_dim], vq = sf[4 * q + 3];
+        const float wv = horner<float, K>(cf, x);
+        const float a2 = lane_fetch(wv, src2[0]);
+        const float a1 = lane_fetch(wv, src1[0]);
+        fmac_row_bcast8(a8, wv, vq * a1 * a2);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  } else
   for (int base_p = q0; base_p < q1; base_p += 64) {
     const int p = base_p + lane;
     const bool ok = p < q1;
