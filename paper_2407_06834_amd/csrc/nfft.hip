@@ -667,14 +667,29 @@ k_fold3m(const WinDev* __restrict__ wins, const Fold3Job* __restrict__ jobs, int
       if constexpr (G::bs(n) > 0) {
         if (ns[n] == 0) return;                               // uniform: empty neighbour tile
         const long long src = (long long)s0t[n] * slot_stride + G::base(n);
-        T val[G::nit(n)];
+        constexpr int NI = G::nit(n);
+        // KB slots per round: their NI * KB loads are issued together (the last slot is
+        // reloaded past the end), then added in slot order, as a one-at-a-time sum would
+        constexpr int KB = NI <= 2 ? 8 : (NI <= 4 ? 4 : 2);
+        T val[NI];
 #pragma unroll
-        for (int it = 0; it < G::nit(n); ++it) {
-          const int e = lane + 64 * it;
-          const int ec = e < G::bs(n) ? e : 0;
-          T sum = (T)0;
-          for (int k = 0; k < ns[n]; ++k) sum += padded[src + (long long)k * slot_stride + ec];
-          val[it] = sum;
+        for (int it = 0; it < NI; ++it) val[it] = (T)0;
+        for (int k = 0; k < ns[n]; k += KB) {
+          T ld[KB][NI];
+#pragma unroll
+          for (int j = 0; j < KB; ++j) {
+            const long long so = src + (long long)min(k + j, ns[n] - 1) * slot_stride;
+#pragma unroll
+            for (int it = 0; it < NI; ++it) {
+              const int e = lane + 64 * it;
+              ld[j][it] = padded[so + (e < G::bs(n) ? e : 0)];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < KB; ++j)
+            if (k + j < ns[n])
+#pragma unroll
+              for (int it = 0; it < NI; ++it) val[it] += ld[j][it];
         }
         add_block(n_c, val);
       }
