@@ -269,6 +269,21 @@ __global__ void k_cg_finish(const ImgDev* __restrict__ imgs) {
     u[i] = constant ? f[i] : (T)(mf + (double)z[i]);
 }
 
+// per-block maxima of x (grid-stride), the first stage of max_eta
+__global__ void k_max_part(const double* __restrict__ x, long long N, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double m = -INFINITY;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < N; i += (long long)gridDim.x * 256)
+    m = fmax(m, x[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 __global__ void k_max(const double* __restrict__ x, long long N, double* __restrict__ out) {
   __shared__ double sh[1024];
   double m = -INFINITY;
@@ -452,9 +467,14 @@ nld_status run_pcg_t(Plan& P, double alpha, const void* f, void* u, const nld_pc
 }  // namespace
 
 void compute_max_eta(Plan& P, hipStream_t s) {
+  // per-block maxima over 1024 blocks, then their maximum (max is exact in any order)
+  constexpr int kParts = 1024;
   double* d = nullptr;
-  NLD_HIP(hipMallocAsync((void**)&d, sizeof(double), s));
-  hipLaunchKernelGGL(k_max, dim3(1), dim3(1024), 0, s, P.D, (long long)P.N, d);
+  NLD_HIP(hipMallocAsync((void**)&d, (kParts + 1) * sizeof(double), s));
+  const long long nb = std::max<long long>(1, std::min<long long>(kParts, (P.N + 255) / 256));
+  hipLaunchKernelGGL(k_max_part, dim3((unsigned)nb), dim3(256), 0, s, P.D, (long long)P.N, d + 1);
+  NLD_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_max, dim3(1), dim3(1024), 0, s, (const double*)(d + 1), nb, d);
   NLD_HIP(hipGetLastError());
   double mx = 0.0;
   NLD_HIP(hipMemcpyAsync(&mx, d, sizeof(double), hipMemcpyDeviceToHost, s));

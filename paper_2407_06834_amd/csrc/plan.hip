@@ -93,12 +93,17 @@ struct CoordParams {
 
 __device__ inline int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a + b - 1) / b); }
 
-// Grid coordinates of every (window, node): packed base cell, fractional offsets and the
-// global key of the tile that holds the base cell.
+// Grid coordinates of every (window, node): packed base cell and fractional offsets in one
+// entry (16 bytes in FP32, 32 in FP64, so that the permutation into sorted order reads one
+// cache line per entry), and the global key of the tile that holds the base cell.
+template <typename T> struct CoordEntry;
+template <> struct __attribute__((aligned(16))) CoordEntry<float> { unsigned base; float f[3]; };
+template <> struct __attribute__((aligned(16))) CoordEntry<double> { unsigned base, pad; double f[3]; };
+
 template <typename T>
 __global__ void k_coords(const T* __restrict__ F, long long N, int L,
-                         const CoordParams* __restrict__ cp, unsigned* __restrict__ base,
-                         T* __restrict__ frac, unsigned* __restrict__ key) {
+                         const CoordParams* __restrict__ cp, CoordEntry<T>* __restrict__ ent,
+                         unsigned* __restrict__ key) {
   const long long total = N * L;
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
@@ -106,6 +111,7 @@ __global__ void k_coords(const T* __restrict__ F, long long N, int L,
     const long long j = idx - (long long)l * N;
     const CoordParams p = cp[l];
     int b[3];
+    CoordEntry<T> e{};
     for (int dd = 0; dd < 3; ++dd) {
       T fr = (T)0;
       int bi = 0;
@@ -120,9 +126,10 @@ __global__ void k_coords(const T* __restrict__ F, long long N, int L,
         bi = ((bi % p.n[dd]) + p.n[dd]) % p.n[dd];
       }
       b[dd] = bi;
-      frac[((long long)l * 3 + dd) * N + j] = fr;
+      e.f[dd] = fr;
     }
-    base[idx] = (unsigned)b[0] | ((unsigned)b[1] << 8) | ((unsigned)b[2] << 16);
+    e.base = (unsigned)b[0] | ((unsigned)b[1] << 8) | ((unsigned)b[2] << 16);
+    ent[idx] = e;
     const int g = ((b[0] / p.ts[0]) * p.nts[1] + b[1] / p.ts[1]) * p.nts[2] + b[2] / p.ts[2];
     const int lc = ((b[0] % p.ts[0]) * p.ts[1] + b[1] % p.ts[1]) * p.ts[2] + b[2] % p.ts[2];
     key[idx] = ((p.tile_off + (unsigned)g) << p.cell_bits) | (unsigned)lc;
@@ -385,16 +392,17 @@ void radix_sort_pairs(unsigned* keys, unsigned* vals, long long n, int key_bits,
 // Copy the coordinates of sorted entries: out[e] = in[(window of e, node of e)].
 template <typename T>
 __global__ void k_gather_entries(const unsigned* __restrict__ vals, long long n, long long N,
-                                 const unsigned* __restrict__ base, const T* __restrict__ frac,
-                                 int* __restrict__ out_idx, unsigned* __restrict__ out_base,
-                                 T* __restrict__ out_frac, long long out_stride) {
+                                 const CoordEntry<T>* __restrict__ ent, int* __restrict__ out_idx,
+                                 unsigned* __restrict__ out_base, T* __restrict__ out_frac,
+                                 long long out_stride) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x) {
     const unsigned flat = vals[e];
     const long long l = flat / N, j = flat - l * N;
+    const CoordEntry<T> c = ent[flat];
     out_idx[e] = (int)j;
-    out_base[e] = base[flat];
-    for (int dd = 0; dd < 3; ++dd) out_frac[dd * out_stride + e] = frac[(l * 3 + dd) * N + j];
+    out_base[e] = c.base;
+    for (int dd = 0; dd < 3; ++dd) out_frac[dd * out_stride + e] = c.f[dd];
   }
 }
 
@@ -820,11 +828,10 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   const long long LN = N * L;
   CoordParams* d_cp = dalloc<CoordParams>(L, s);
   upload(P, d_cp, cp.data(), L * sizeof(CoordParams), s);
-  unsigned* base = dalloc<unsigned>(LN, s);
-  T* frac = dalloc<T>(3 * LN, s);
+  CoordEntry<T>* ent = dalloc<CoordEntry<T>>(LN, s);
   unsigned* key = dalloc<unsigned>(LN, s);
   hipLaunchKernelGGL(k_coords<T>, dim3(grid_for(LN)), dim3(256), 0, s, (const T*)features, N, L, d_cp,
-                     base, frac, key);
+                     ent, key);
   NLD_HIP(hipGetLastError());
 
   // ---- 4. nodes of every window sorted (stably) by tile; tile offsets by binary search
@@ -835,20 +842,28 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   while ((1u << kbits) < tile_total) ++kbits;
   if (kbits + cell_bits > 32) throw std::invalid_argument("too many tiles");
   radix_sort_pairs(key, val, LN, kbits + cell_bits, s);
-  P.g_idx = dalloc<int>(LN, s);
-  P.g_base = dalloc<unsigned>(LN, s);
-  P.g_frac = dalloc<T>(3 * LN, s);
-  hipLaunchKernelGGL(k_gather_entries<T>, dim3(grid_for(LN)), dim3(256), 0, s, val, LN, N, base,
-                     frac, P.g_idx, P.g_base, (T*)P.g_frac, LN);
-  NLD_HIP(hipGetLastError());
+  // tile offsets first: the host builds the schedules from them while the device permutes the
+  // node entries into sorted order
   unsigned* toff = dalloc<unsigned>(tile_total + 1, s);
   hipLaunchKernelGGL(k_key_offsets, dim3((tile_total + 256) / 256), dim3(256), 0, s, key, LN,
                      (int)tile_total, cell_bits, toff);
   NLD_HIP(hipGetLastError());
-  std::vector<unsigned> ht(tile_total + 1);
-  NLD_HIP(hipMemcpyAsync(ht.data(), toff, (tile_total + 1) * sizeof(unsigned), hipMemcpyDeviceToHost, s));
-  NLD_HIP(hipStreamSynchronize(s));
-  staging_done(P, s);
+  unsigned* ht_pin = (unsigned*)pinned_get((tile_total + 1) * sizeof(unsigned), false);
+  NLD_HIP(hipMemcpyAsync(ht_pin, toff, (tile_total + 1) * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  hipEvent_t ev_off;
+  NLD_HIP(hipEventCreateWithFlags(&ev_off, hipEventDisableTiming));
+  NLD_HIP(hipEventRecord(ev_off, s));
+  P.g_idx = dalloc<int>(LN, s);
+  P.g_base = dalloc<unsigned>(LN, s);
+  P.g_frac = dalloc<T>(3 * LN, s);
+  hipLaunchKernelGGL(k_gather_entries<T>, dim3(grid_for(LN)), dim3(256), 0, s, val, LN, N,
+                     (const CoordEntry<T>*)ent, P.g_idx, P.g_base, (T*)P.g_frac, LN);
+  NLD_HIP(hipGetLastError());
+  const hipError_t ev_err = hipEventSynchronize(ev_off);
+  (void)hipEventDestroy(ev_off);
+  NLD_HIP(ev_err);
+  std::vector<unsigned> ht(ht_pin, ht_pin + tile_total + 1);
+  pinned_put(ht_pin);
   if (ht[tile_total] != (unsigned)LN) throw std::runtime_error("internal: tile offsets do not add up");
 
   // ---- 5. schedules (host): chunks of the nodes of every non-empty tile, grouped by t;
@@ -1120,8 +1135,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   for (int g = 0; g < 3; ++g) lu.pjob_begin[g] = 0;
 
   dfree(d_cp, s);
-  dfree(base, s);
-  dfree(frac, s);
+  dfree(ent, s);
   dfree(key, s);
   dfree(val, s);
   dfree(toff, s);
