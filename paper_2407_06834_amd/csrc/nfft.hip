@@ -230,7 +230,8 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   // FP32, 3 kept dimensions, 8 taps (m = 4): every row of 16 lanes holds the first dimension's
   // weights in its lanes 0-7 (the row broadcast of fmac_row_bcast8 reads them there); lanes
   // 8-15 hold the second dimension's in rows 0 and 2 and the third's in rows 1 and 3.  A node's
-  // x = 2 f - 1 per dimension and its scaled value are staged per wavefront in LDS.
+  // x = 2 f - 1 per dimension and its scaled value are staged per wavefront in LDS.  The
+  // polynomials of two consecutive nodes are evaluated in one pass (one per half wavefront).
   constexpr bool kDpp = TD == 3 && W == 8 && sizeof(T) == 4;
   __shared__ float4 s_stage[kDpp ? kSpreadWaves * 64 : 1];
   static_assert(TD * W <= 64, "one lane per tap and dimension");
@@ -321,17 +322,28 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
       __builtin_amdgcn_wave_barrier();
       const LdsPtr<float> sf = (LdsPtr<float>)stg;
       const int cnt = __builtin_amdgcn_readfirstlane(min(64, q1 - base_p));
-      for (int q = 0; q < cnt; ++q) {
+      // two nodes per polynomial pass: lanes 0-31 evaluate node q's weights and lanes 32-63
+      // node q + 1's (same layout within each half); v_permlane32_swap of the result with
+      // itself gives each half's values replicated in both halves, the layout one node uses
+      const int half = lane >> 5;
+      auto node = [&](int q, float wv) {
         const unsigned bq = __builtin_amdgcn_readfirstlane(lane_bcast(mb, q));
         if (bq != cur) {
           if (cur != kNone) flush();
           cur = bq;
         }
-        const float x = sf[4 * q + my_dim], vq = sf[4 * q + 3];
-        const float wv = horner<float, K>(cf, x);
+        const float vq = sf[4 * q + 3];
         const float a2 = lane_fetch(wv, src2[0]);
         const float a1 = lane_fetch(wv, src1[0]);
         fmac_row_bcast8(a8, wv, vq * a1 * a2);
+      };
+      for (int q = 0; q < cnt; q += 2) {
+        const float x = sf[4 * (q + half) + my_dim];     // q + half <= 63
+        const float wv = horner<float, K>(cf, x);
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(wv), __float_as_uint(wv),
+                                                         false, false);
+        node(q, __uint_as_float(sw[0]));
+        if (q + 1 < cnt) node(q + 1, __uint_as_float(sw[1]));
       }
       __builtin_amdgcn_wave_barrier();
     }
