@@ -115,23 +115,37 @@ __device__ __forceinline__ double lane_fetch(double v, int byte_addr) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// acc[i] += w(lane i of this lane's row of 16) * b for i < 8: the row broadcast (DPP
-// row_newbcast) is part of each FMA, so no readlane or separate move is issued.  The leading
-// s_nop covers the two wait states a DPP read needs after a VALU write of its source.  Same
-// single-rounding FMA as fmaf(b, w_i, acc[i]).
-__device__ __forceinline__ void fmac_row_bcast8(float (&acc)[8], float w, float b) {
-  asm("s_nop 1\n\t"
-      "v_fmac_f32_dpp %0, %8, %9 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %1, %8, %9 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %2, %8, %9 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %3, %8, %9 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %4, %8, %9 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %5, %8, %9 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %6, %8, %9 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %7, %8, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf"
-      : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]), "+v"(acc[5]),
-        "+v"(acc[6]), "+v"(acc[7])
-      : "v"(w), "v"(b));
+// acc[i] += w(lane i of this lane's row of 16) * b for i < W (W = 6 or 8): the row broadcast
+// (DPP row_newbcast) is part of each FMA, so no readlane or separate move is issued.  The
+// leading s_nop covers the two wait states a DPP read needs after a VALU write of its source.
+// Same single-rounding FMA as fmaf(b, w_i, acc[i]).
+template <int W>
+__device__ __forceinline__ void fmac_row_bcast(float (&acc)[W], float w, float b) {
+  static_assert(W == 6 || W == 8, "row broadcast FMAs for 6 or 8 taps");
+  if constexpr (W == 8) {
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %8, %9 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %8, %9 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %8, %9 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %8, %9 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %8, %9 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %5, %8, %9 row_newbcast:5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %6, %8, %9 row_newbcast:6 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %7, %8, %9 row_newbcast:7 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]), "+v"(acc[5]),
+          "+v"(acc[6]), "+v"(acc[7])
+        : "v"(w), "v"(b));
+  } else {
+    asm("s_nop 1\n\t"
+        "v_fmac_f32_dpp %0, %6, %7 row_newbcast:0 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %1, %6, %7 row_newbcast:1 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %2, %6, %7 row_newbcast:2 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %3, %6, %7 row_newbcast:3 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %4, %6, %7 row_newbcast:4 row_mask:0xf bank_mask:0xf\n\t"
+        "v_fmac_f32_dpp %5, %6, %7 row_newbcast:5 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]), "+v"(acc[5])
+        : "v"(w), "v"(b));
+  }
 }
 
 // Weights of the W = 2m taps of one node in one dimension (tap i at cell floor(u) - m + 1 + i,
@@ -227,15 +241,16 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   // [W, 2W) the second's, [2W, 3W) the third's (one polynomial per lane and node); the lane that
   // owns tap pair (i1, i2) of the last two dimensions fetches its two factors with ds_bpermute,
   // and the first dimension's W weights are broadcast to every lane.
-  // FP32, 3 kept dimensions, 8 taps (m = 4): every row of 16 lanes holds the first dimension's
-  // weights in its lanes 0-7 (the row broadcast of fmac_row_bcast8 reads them there); lanes
-  // 8-15 hold the second dimension's in rows 0 and 2 and the third's in rows 1 and 3.  A node's
+  // FP32, 3 kept dimensions, W = 6 or 8 taps (m = 3 or 4): every row of 16 lanes holds the
+  // first dimension's weights in its lanes 0..W-1 (the row broadcast of fmac_row_bcast reads
+  // them there); lanes 8..8+W-1 hold the second dimension's in rows 0 and 2 and the third's in
+  // rows 1 and 3 (lanes of a row past W evaluate the last tap's polynomial, unused).  A node's
   // x = 2 f - 1 per dimension and its scaled value are staged per wavefront in LDS.  The
   // polynomials of two consecutive nodes are evaluated in one pass (one per half wavefront).
-  constexpr bool kDpp = TD == 3 && W == 8 && sizeof(T) == 4;
+  constexpr bool kDpp = TD == 3 && (W == 6 || W == 8) && sizeof(T) == 4;
   __shared__ float4 s_stage[kDpp ? kSpreadWaves * 64 : 1];
   static_assert(TD * W <= 64, "one lane per tap and dimension");
-  const int my_tap = kDpp ? (lane & 7) : lane % W;
+  const int my_tap = kDpp ? min(lane & 7, W - 1) : lane % W;
   const int my_dim = kDpp ? ((lane & 8) ? 1 + ((lane >> 4) & 1) : 0)
                           : lane / W;               // lanes with my_dim >= TD idle here
   // x = 2 f - 1 of this lane's dimension as three FMAs with per-lane factors 2 or 0 (a node's
@@ -307,7 +322,7 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     // order, so the stores are visible to the loads of the node loop below and the next
     // round's stores follow them
     float4* stg = s_stage + wave * 64;
-    float (&a8)[8] = accr[0];
+    float (&aw)[W] = accr[0];
     for (int base_p = q0; base_p < q1; base_p += 64) {
       const int p = base_p + lane;
       const bool ok = p < q1;
@@ -335,7 +350,7 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
         const float vq = sf[4 * q + 3];
         const float a2 = lane_fetch(wv, src2[0]);
         const float a1 = lane_fetch(wv, src1[0]);
-        fmac_row_bcast8(a8, wv, vq * a1 * a2);
+        fmac_row_bcast<W>(aw, wv, vq * a1 * a2);
       };
       for (int q = 0; q < cnt; q += 2) {
         const float x = sf[4 * (q + half) + my_dim];     // q + half <= 63

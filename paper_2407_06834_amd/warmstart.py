@@ -35,6 +35,8 @@ from .synth import make_image
 TRAIN_SIDES = (256, 384, 512, 768, 1024)
 # grids are capped at 128 points per dimension (windows with M = 96 oversample by 4/3)
 MAX_GRID = 128
+# window cutoff of the plans (2m taps per dimension); the product stays within 1e-4 at m = 3
+CUTOFF = 3
 RHO = 2
 
 
@@ -98,7 +100,7 @@ def generate(seeds, sides=TRAIN_SIDES, batch=16, tol=1e-6, log=None):
         for p in chunk:
             img = torch.tensor(p["f"], dtype=torch.float32, device="cuda")
             F = nld.features_from_image(img, RHO)
-            plan = nld.Plan(F, wins, p["sigma"], [1.0] * 9, cutoff=4, matvec_tol=1e-4,
+            plan = nld.Plan(F, wins, p["sigma"], [1.0] * 9, cutoff=CUTOFF, matvec_tol=1e-4,
                             max_grid=MAX_GRID)
             alphas.append(problem_alpha(p, plan.degree_vector(), 9.0))
             plans.append(plan)
@@ -150,7 +152,7 @@ def evaluate(net: WarmStartNet, seeds, side=2048, tol=1e-6, log=None):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F = nld.features_from_image(img, RHO)
-        plan = nld.Plan(F, wins, p["sigma"], [1.0] * 9, cutoff=4, matvec_tol=1e-4,
+        plan = nld.Plan(F, wins, p["sigma"], [1.0] * 9, cutoff=CUTOFF, matvec_tol=1e-4,
                             max_grid=MAX_GRID)
         alpha = problem_alpha(p, plan.degree_vector(), 9.0)
         torch.cuda.synchronize()

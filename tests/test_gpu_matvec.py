@@ -83,12 +83,13 @@ def test_matvec_fp64_stated_bandwidth_error_is_reported():
     assert 1e-7 < err < 1e-2
 
 
-def test_matvec_fp32_vs_oracle():
+@pytest.mark.parametrize("cutoff", [3, 4])
+def test_matvec_fp32_vs_oracle(cutoff):
     torch = torch_gpu()
     _, nld, f, img, F = _setup(48, 40, 1, 3, torch.float32)
     wins = nld.window_table(1)
     sig, wts = [0.1, 0.15, 0.2, 0.12], [1.0, 0.5, 2.0, 1.5]
-    plan = nld.Plan(F, wins, sig, wts, bandwidth=64, cutoff=4)
+    plan = nld.Plan(F, wins, sig, wts, bandwidth=64, cutoff=cutoff)
     F64 = F.double().cpu().numpy()
     v = np.random.default_rng(3).standard_normal(F64.shape[1])
     y = plan.anova_matvec(torch.tensor(v, dtype=torch.float32, device="cuda")).cpu().numpy()

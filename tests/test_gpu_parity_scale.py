@@ -1,9 +1,9 @@
 """Parity at the largest workloads, against the oracle only.
 
 * 2048 x 2048 (the learned-warm-start evaluation size): the FP32 product in the launch
-  configuration that solves there (5x5 patch + position in 9 windows, m = 4, bandwidth chosen
-  per window for a 1e-4 product, grids capped at 128 points), on sampled rows (corners, edges, a
-  seeded sample) against the oracle's exact FP64 direct sums.
+  configurations that solve there (5x5 patch + position in 9 windows, m = 3 or 4, bandwidth
+  chosen per window for a 1e-4 product, grids capped at 128 points), on sampled rows (corners,
+  edges, a seeded sample) against the oracle's exact FP64 direct sums.
 * 512 x 512 at sigma = 0.05: the automatic bandwidth reaches the product tolerance that the
   stated M = 64 misses (FP32 1e-4, FP64 1e-6).
 * 256 x 256: the FP64 solve against the stored exact-kernel solution that
@@ -36,6 +36,7 @@ def _product_rows(torch, nld, f, sig, rows, **plan_kw):
     F = nld.features_from_image(img, 2)
     wins = nld.window_table(2)
     plan = nld.Plan(F, wins, sig, [1.0] * len(wins), **plan_kw)
+    grids = [(plan.window_info(l).bandwidth, plan.window_info(l).grid) for l in range(len(wins))]
     v = random_vector(31, F.shape[1])
     y = plan.anova_matvec(torch.tensor(v, dtype=torch.float32, device="cuda")).cpu().numpy()
     plan.close()
@@ -43,24 +44,33 @@ def _product_rows(torch, nld, f, sig, rows, **plan_kw):
     del F
     ref = csum.anova_rows(F64, wins, sig, [1.0] * len(wins),
                           v.astype(np.float32).astype(np.float64), rows)
-    return y[rows], ref
+    return y[rows], ref, grids
 
 
-@pytest.mark.parametrize("cell,max_grid", [("drawn", 0), ("fixed", 0), ("drawn", 128)])
-def test_2048_product_on_sampled_rows(cell, max_grid):
+@pytest.mark.parametrize("cell,max_grid,cutoff", [("drawn", 0, 4), ("fixed", 0, 4), ("eval304", 128, 4),
+                                                  ("eval304", 128, 3)])
+def test_2048_product_on_sampled_rows(cell, max_grid, cutoff):
     torch = torch_gpu()
     from paper_2407_06834_amd import nld
     side = 2048
-    rng = np.random.default_rng(300)
-    if cell == "drawn":       # widths drawn per window as for the evaluation images
-        sig = [float(x) for x in rng.uniform(0.05, 0.2, 9)]
-    else:                     # the fixed cell: sigma_l = 0.1
-        sig = [0.1] * 9
-    _, f = make_image(300, side, side, 20, 12, 0.1)
+    if cell == "eval304":     # an evaluation image and its drawn widths: three windows need M = 96
+        from paper_2407_06834_amd.warmstart import draw_problem
+        p = draw_problem(304, side=side, noise=0.1)
+        sig, f = p["sigma"], p["f"]
+    else:
+        rng = np.random.default_rng(300)
+        if cell == "drawn":   # widths drawn per window as for the evaluation images
+            sig = [float(x) for x in rng.uniform(0.05, 0.2, 9)]
+        else:                 # the fixed cell: sigma_l = 0.1
+            sig = [0.1] * 9
+        _, f = make_image(300, side, side, 20, 12, 0.1)
     rows = _rows(side, side, 200, 7)
-    print(f"2048^2 product, cell {cell}, max_grid {max_grid}, sigma {np.round(sig, 3).tolist()}",
-          flush=True)
-    y, ref = _product_rows(torch, nld, f, sig, rows, cutoff=4, matvec_tol=1e-4, max_grid=max_grid)
+    print(f"2048^2 product, cell {cell}, max_grid {max_grid}, m {cutoff}, "
+          f"sigma {np.round(sig, 3).tolist()}", flush=True)
+    y, ref, grids = _product_rows(torch, nld, f, sig, rows, cutoff=cutoff, matvec_tol=1e-4,
+                                  max_grid=max_grid)
+    if cell == "eval304":     # the grid cap is exercised: M = 96 on 128-point grids
+        assert (96, 128) in grids, grids
     assert rel(y, ref) < 1e-4, rel(y, ref)
     assert max_rel(y, ref) < 4e-4, max_rel(y, ref)
 
