@@ -341,11 +341,14 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
       // node q + 1's (same layout within each half); v_permlane32_swap of the result with
       // itself gives each half's values replicated in both halves, the layout one node uses
       const int half = lane >> 5;
+      // nodes that start a run (their cell differs from the previous node's): one ballot per
+      // round, so the per-node test is a scalar bit test and the cell is read only at a run start
+      const unsigned prev_mb = (unsigned)__builtin_amdgcn_ds_bpermute(((lane + 63) & 63) * 4, (int)mb);
+      const unsigned long long starts = __ballot(ok && mb != (lane == 0 ? cur : prev_mb));
       auto node = [&](int q, float wv) {
-        const unsigned bq = __builtin_amdgcn_readfirstlane(lane_bcast(mb, q));
-        if (bq != cur) {
+        if ((starts >> q) & 1ull) {
           if (cur != kNone) flush();
-          cur = bq;
+          cur = __builtin_amdgcn_readfirstlane(lane_bcast(mb, q));
         }
         const float vq = sf[4 * q + 3];
         const float a2 = lane_fetch(wv, src2[0]);
