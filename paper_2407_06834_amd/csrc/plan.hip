@@ -305,42 +305,52 @@ void exclusive_scan(unsigned* data, long long n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- stable LSD radix sort
-// 8-bit digits, one wave of 64 lanes per block and 1024 items per block.  Within a block
-// the items are ranked in order with wave ballots, so equal keys keep their input order.
-constexpr int kSortLanes = 64, kSortRounds = 16, kSortItems = kSortLanes * kSortRounds;
+// 8-bit digits, blocks of 4 wavefronts and 4096 items.  A wavefront ranks its 1024 items in
+// order with ballots (equal keys keep their input order), the block places its items in digit
+// order in LDS, and then writes every digit's run to its global position with consecutive
+// threads on consecutive positions (runs of 16 items on average where the digits are random,
+// instead of single items).
+constexpr int kSortThreads = 256, kSortPer = 16, kSortItems = kSortThreads * kSortPer;
+constexpr int kSortWaveItems = kSortItems / (kSortThreads / 64);
 
-__global__ void __launch_bounds__(kSortLanes)
+__global__ void __launch_bounds__(kSortThreads)
 k_radix_hist(const unsigned* __restrict__ keys, long long n, int shift, unsigned* __restrict__ hist,
              int nblk) {
   __shared__ unsigned h[256];
-  for (int i = threadIdx.x; i < 256; i += kSortLanes) h[i] = 0;
+  h[threadIdx.x] = 0;
   __syncthreads();
   const long long b0 = (long long)blockIdx.x * kSortItems;
-  for (int r = 0; r < kSortRounds; ++r) {
-    const long long i = b0 + r * kSortLanes + threadIdx.x;
+  for (int r = 0; r < kSortPer; ++r) {
+    const long long i = b0 + r * kSortThreads + threadIdx.x;
     if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  for (int dgt = threadIdx.x; dgt < 256; dgt += kSortLanes)
-    hist[(long long)dgt * nblk + blockIdx.x] = h[dgt];
+  hist[(long long)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(kSortLanes)
+__global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const unsigned* __restrict__ kin, const unsigned* __restrict__ vin,
                 unsigned* __restrict__ kout, unsigned* __restrict__ vout, long long n, int shift,
                 const unsigned* __restrict__ offs, int nblk) {
-  __shared__ unsigned cur[256];
-  for (int dgt = threadIdx.x; dgt < 256; dgt += kSortLanes)
-    cur[dgt] = offs[(long long)dgt * nblk + blockIdx.x];
+  constexpr int kWaves = kSortThreads / 64;
+  __shared__ unsigned wcnt[kWaves][256];    // per-wavefront counts, then their prefixes
+  __shared__ unsigned lstart[256];          // first block-local position of every digit
+  __shared__ unsigned goff[256];            // first global position of every digit (this block)
+  __shared__ unsigned wsum[kWaves];
+  __shared__ unsigned skey[kSortItems], sval[kSortItems];
+  const int t = threadIdx.x, lane = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+  for (int d = t; d < kWaves * 256; d += kSortThreads) (&wcnt[0][0])[d] = 0u;
+  goff[t] = offs[(long long)t * nblk + blockIdx.x];
   __syncthreads();
-  const int lane = threadIdx.x;
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const long long b0 = (long long)blockIdx.x * kSortItems;
-  for (int r = 0; r < kSortRounds; ++r) {
-    const long long i = b0 + r * kSortLanes + lane;
+  const long long b0 = (long long)blockIdx.x * kSortItems + (long long)wv * kSortWaveItems;
+  unsigned key[kSortPer], val[kSortPer], pos[kSortPer];   // pos: digit << 16 | rank in wavefront
+  for (int r = 0; r < kSortPer; ++r) {
+    const long long i = b0 + r * 64 + lane;
     const bool valid = i < n;
-    const unsigned key = valid ? kin[i] : 0u;
-    const unsigned dg = (key >> shift) & 255u;
+    const unsigned k = valid ? kin[i] : 0u;
+    const unsigned dg = (k >> shift) & 255u;
     unsigned long long mask = __ballot(valid);
     for (int bit = 0; bit < 8; ++bit) {
       const bool set = (dg >> bit) & 1u;
@@ -349,15 +359,53 @@ k_radix_scatter(const unsigned* __restrict__ kin, const unsigned* __restrict__ v
     }
     const unsigned rank = (unsigned)__popcll(mask & below);
     const unsigned group = (unsigned)__popcll(mask);
-    unsigned dst = 0;
-    if (valid) dst = cur[dg] + rank;
-    __syncthreads();
-    if (valid) {
-      kout[dst] = key;
-      vout[dst] = vin[i];
-      if (rank == group - 1) cur[dg] += group;
-    }
-    __syncthreads();
+    // every lane reads its digit's count before the last lane of each group stores the new one
+    // (LDS operations of a wavefront execute in order)
+    const unsigned base = wcnt[wv][dg];
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == group - 1) wcnt[wv][dg] = base + group;
+    __builtin_amdgcn_wave_barrier();
+    key[r] = k;
+    val[r] = valid ? vin[i] : 0u;
+    pos[r] = valid ? ((dg << 16) | (base + rank)) : 0xffffffffu;
+  }
+  __syncthreads();
+  // digit t: prefixes over the wavefronts and the block-local start (exclusive scan of totals)
+  unsigned c[kWaves], tot = 0;
+  for (int w = 0; w < kWaves; ++w) {
+    c[w] = tot;
+    tot += wcnt[w][t];
+  }
+  unsigned inc = tot;
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned y = __shfl_up(inc, off);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  unsigned before = 0;
+  for (int w = 0; w < wv; ++w) before += wsum[w];
+  lstart[t] = before + inc - tot;
+  for (int w = 0; w < kWaves; ++w) wcnt[w][t] = c[w];
+  __syncthreads();
+  for (int r = 0; r < kSortPer; ++r) {
+    if (pos[r] == 0xffffffffu) continue;
+    const unsigned dg = pos[r] >> 16;
+    const unsigned q = lstart[dg] + wcnt[wv][dg] + (pos[r] & 0xffffu);
+    skey[q] = key[r];
+    sval[q] = val[r];
+  }
+  __syncthreads();
+  const long long nv = n - (long long)blockIdx.x * kSortItems;
+  const int nvalid = nv < kSortItems ? (int)nv : kSortItems;
+  for (int r = 0; r < kSortPer; ++r) {
+    const int q = r * kSortThreads + t;
+    if (q >= nvalid) break;
+    const unsigned k = skey[q];
+    const unsigned dg = (k >> shift) & 255u;
+    const unsigned dst = goff[dg] + (unsigned)q - lstart[dg];
+    kout[dst] = k;
+    vout[dst] = sval[q];
   }
 }
 
@@ -371,10 +419,10 @@ void radix_sort_pairs(unsigned* keys, unsigned* vals, long long n, int key_bits,
   unsigned *ka = keys, *va = vals, *kb = k2, *vb = v2;
   const int passes = std::max(1, (key_bits + 7) / 8);
   for (int pss = 0; pss < passes; ++pss) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortLanes), 0, s, ka, n, 8 * pss, hist, nblk);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, s, ka, n, 8 * pss, hist, nblk);
     NLD_HIP(hipGetLastError());
     exclusive_scan(hist, 256LL * nblk, s);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortLanes), 0, s, ka, va, kb, vb, n,
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortThreads), 0, s, ka, va, kb, vb, n,
                        8 * pss, hist, nblk);
     NLD_HIP(hipGetLastError());
     std::swap(ka, kb);
