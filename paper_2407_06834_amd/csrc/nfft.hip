@@ -28,6 +28,8 @@ constexpr int kSpreadWaves = 4;
 constexpr int kSpreadThreads = 64 * kSpreadWaves;
 constexpr int kConvThreads = 256;
 constexpr int kGatherThreads = 256;
+constexpr int kAbsBlocks = 64;       // blocks per image of k_absmax (at most one wavefront's lanes)
+static_assert(kAbsBlocks <= 64 && kAbsBlocks <= kRedBlocks, "absmax partials: one per lane, inside the scratch");
 
 __device__ __forceinline__ int wrap(int c, int n) {
   c %= n;
@@ -176,6 +178,32 @@ __device__ __forceinline__ void poly_row(P psi, T fr, T* wt) {
 // TSC = 8: every 3-D window of the launch has 8^3 tiles, so the padded extents and strides are
 // compile-time constants (LDS offsets fold into the instructions); TSC = 0 reads them from the
 // window descriptor.
+// Per-block maxima of |v| of every image of the launch (blockIdx.y), written to slot 7 of the
+// image's FP64 reduction scratch (the grid reductions use slots 0-4 and consume them within
+// their kernel); the spreading derives its fixed-point scales from them.  A NaN propagates.
+template <typename T>
+__global__ void __launch_bounds__(256) k_absmax(const ImgDev* __restrict__ imgs, VecArg in, int check) {
+  const ImgDev& im = imgs[blockIdx.y];
+  if (check && im.st->done) return;
+  const T* v = vin<T>(im, in);
+  double m = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < im.N; i += (long long)kAbsBlocks * 256) {
+    const double a = fabs((double)v[i]);
+    m = (a > m || a != a) ? a : m;
+  }
+  __shared__ double sh[256];
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      const double o = sh[threadIdx.x + k];
+      if (o > sh[threadIdx.x] || o != o) sh[threadIdx.x] = o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) im.red[(size_t)blockIdx.x * 8 + 7] = sh[0];
+}
+
 template <typename T, int W, int TD, int TSC>
 __global__ void __launch_bounds__(kSpreadThreads)
 k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int job0,
@@ -208,7 +236,6 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   extern __shared__ unsigned char smem_raw[];
   Acc* acc = reinterpret_cast<Acc*>(smem_raw);
   Acc* acc_lo = acc + (kTwo ? w.pe[0] * w.pe[1] * w.pe[2] : 0);
-  __shared__ double s_part[kSpreadWaves];
   constexpr int PEC = (TD == 3 && TSC > 0) ? TSC + W - 1 : 0;
   const int pe1 = PEC ? PEC : w.pe[1], pe2 = PEC ? PEC : w.pe[2];
   const int cells = PEC ? PEC * PEC * PEC : w.pe[0] * pe1 * pe2;
@@ -219,15 +246,13 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     acc[c] = (Acc)0;
     if constexpr (kTwo) acc_lo[c] = (Acc)0;
   }
-  // fixed-point scale of this chunk
-  double sa = 0.0;
-  for (int p = job.pbeg + threadIdx.x; p < job.pend; p += kSpreadThreads)
-    sa += fabs((double)v[g_idx[p]]);
-  for (int off = 32; off > 0; off >>= 1) sa += __shfl_xor(sa, off);
-  if (lane == 0) s_part[wave] = sa;
+  // fixed-point scale of this chunk from a bound of sum |v| over its nodes: max |v| of the
+  // image (per-block maxima left by k_absmax in slot 7 of the image's reduction scratch) times
+  // the chunk's node count
+  double vmax = lane < kAbsBlocks ? im.red[lane * 8 + 7] : 0.0;
+  for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
   __syncthreads();
-  double tot = 0.0;
-  for (int k = 0; k < kSpreadWaves; ++k) tot += s_part[k];
+  const double tot = vmax * (double)(job.pend - job.pbeg);
   auto out = padded + (long long)job.slot * slot_stride;
   if (!(tot > 0.0)) {
     for (int c = threadIdx.x; c < cells; c += kSpreadThreads) out[c] = (T)0;
@@ -1363,6 +1388,11 @@ void launch_tiles(const LaunchSet& ls, VecArg in, int check, hipStream_t s, bool
   // spreading accumulates in fixed point: two 32-bit words (FP32) or one 64-bit word (FP64) per
   // cell; gathering stages the tile in T
   const size_t lds = (size_t)ls.max_padded * (gather ? sizeof(T) : 8);
+  if (!gather) {
+    hipLaunchKernelGGL(k_absmax<T>, dim3(kAbsBlocks, ls.n_imgs), dim3(256), 0, s, ls.d_imgs, in,
+                       check);
+    NLD_HIP(hipGetLastError());
+  }
   for (int g = 0; g < 3; ++g) {
     const int j0 = ls.tjob_begin[g], nj = ls.tjob_begin[g + 1] - j0;
     if (nj == 0) continue;
