@@ -1110,15 +1110,31 @@ __device__ __forceinline__ void gather_nodes(const TileJob& job, const WinDev& w
   // explicit address spaces: LDS reads for the staged tile, global loads otherwise
   LdsPtr<T> tile_l = (LdsPtr<T>)tile;
   GlobalPtr<T> h_g = (GlobalPtr<T>)h;
+  // a node's entries are loaded one iteration ahead, so their latency overlaps the previous
+  // node's arithmetic
+  unsigned nb_ = 0u;
+  T nf0 = (T)0, nf1 = (T)0, nf2 = (T)0;
+  int nidx = 0;
+  auto load_node = [&](int q) {
+    nb_ = g_base[q];
+    if constexpr (TD == 3) nf0 = g_frac[q];
+    if constexpr (TD >= 2) nf1 = g_frac[LN + q];
+    nf2 = g_frac[2 * LN + q];
+    nidx = g_idx[q];
+  };
+  if (job.pbeg + (int)threadIdx.x < job.pend) load_node(job.pbeg + threadIdx.x);
   for (int p = job.pbeg + threadIdx.x; p < job.pend; p += kGatherThreads) {
-    const unsigned bb = g_base[p];
+    const unsigned bb = nb_;
+    const T fr0 = nf0, fr1 = nf1, fr2 = nf2;
+    const int out_idx = nidx;
+    if (p + kGatherThreads < job.pend) load_node(p + kGatherThreads);
     const int b2 = (int)((bb >> 16) & 255u), b1 = (int)((bb >> 8) & 255u), b0 = (int)(bb & 255u);
     T w2[W];
-    poly_row<T, W>(psi, g_frac[2 * LN + p], w2);
-    const T x1 = (TD >= 2) ? (T)2 * g_frac[LN + p] - (T)1 : (T)0;
+    poly_row<T, W>(psi, fr2, w2);
+    const T x1 = (TD >= 2) ? (T)2 * fr1 - (T)1 : (T)0;
     T w1[BIG ? 1 : W];
-    if constexpr (TD >= 2 && !BIG) poly_row<T, W>(psi, g_frac[LN + p], w1);
-    const T x0 = (TD == 3) ? (T)2 * g_frac[p] - (T)1 : (T)0;
+    if constexpr (TD >= 2 && !BIG) poly_row<T, W>(psi, fr1, w1);
+    const T x0 = (TD == 3) ? (T)2 * fr0 - (T)1 : (T)0;
     int c2[W];
 #pragma unroll
     for (int i2 = 0; i2 < W; ++i2) c2[i2] = STAGED ? b2 - o2 + i2 : wrap(b2 - m + 1 + i2, n2);
@@ -1156,7 +1172,7 @@ __device__ __forceinline__ void gather_nodes(const TileJob& job, const WinDev& w
     } else {
       acc = plane(0);
     }
-    ylocal[g_idx[p]] = acc;
+    ylocal[out_idx] = acc;
   }
 }
 
