@@ -348,15 +348,36 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     // round's stores follow them
     float4* stg = s_stage + wave * 64;
     float (&aw)[W] = accr[0];
+    // the next round's entries are loaded while this round's nodes are spread (the input
+    // value through the node index after the node loop, once the index has arrived)
+    unsigned n_mb = 0u;
+    float n_f0 = 0.0f, n_f1 = 0.0f, n_f2 = 0.0f, n_v = 0.0f;
+    int n_idx = 0;
+    auto load_round = [&](int bp) {
+      const int pp = bp + lane;
+      if (pp < q1) {
+        n_mb = g_base[pp];
+        n_f0 = g_frac[pp];
+        n_f1 = g_frac[LN + pp];
+        n_f2 = g_frac[2 * LN + pp];
+        n_idx = g_idx[pp];
+      }
+    };
+    if (q0 < q1) {
+      load_round(q0);
+      if (q0 + lane < q1) n_v = v[n_idx];
+    }
     for (int base_p = q0; base_p < q1; base_p += 64) {
       const int p = base_p + lane;
       const bool ok = p < q1;
-      const unsigned mb = ok ? g_base[p] : 0u;
+      const unsigned mb = ok ? n_mb : 0u;
       float4 nd;
-      nd.x = ok ? fmaf(g_frac[p], 2.0f, -1.0f) : 0.0f;
-      nd.y = ok ? fmaf(g_frac[LN + p], 2.0f, -1.0f) : 0.0f;
-      nd.z = ok ? fmaf(g_frac[2 * LN + p], 2.0f, -1.0f) : 0.0f;
-      nd.w = ok ? v[g_idx[p]] * scale_t : 0.0f;
+      nd.x = ok ? fmaf(n_f0, 2.0f, -1.0f) : 0.0f;
+      nd.y = ok ? fmaf(n_f1, 2.0f, -1.0f) : 0.0f;
+      nd.z = ok ? fmaf(n_f2, 2.0f, -1.0f) : 0.0f;
+      nd.w = ok ? n_v * scale_t : 0.0f;
+      const bool more = base_p + 64 < q1;
+      if (more) load_round(base_p + 64);
       __builtin_amdgcn_wave_barrier();
       stg[lane] = nd;
       __builtin_amdgcn_wave_barrier();
@@ -388,6 +409,7 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
         node(q, __uint_as_float(sw[0]));
         if (q + 1 < cnt) node(q + 1, __uint_as_float(sw[1]));
       }
+      if (more && base_p + 64 + lane < q1) n_v = v[n_idx];
       __builtin_amdgcn_wave_barrier();
     }
   } else
