@@ -28,8 +28,8 @@ constexpr int kSpreadWaves = 4;
 constexpr int kSpreadThreads = 64 * kSpreadWaves;
 constexpr int kConvThreads = 256;
 constexpr int kGatherThreads = 256;
-constexpr int kAbsBlocks = 64;       // blocks per image of k_absmax (at most one wavefront's lanes)
-static_assert(kAbsBlocks <= 64 && kAbsBlocks <= kRedBlocks, "absmax partials: one per lane, inside the scratch");
+constexpr int kAbsBlocks = 512;      // blocks per image of k_absmax
+static_assert(kAbsBlocks % 64 == 0 && kAbsBlocks <= kRedBlocks, "absmax partials: whole lanes, inside the scratch");
 
 __device__ __forceinline__ int wrap(int c, int n) {
   c %= n;
@@ -181,24 +181,44 @@ __device__ __forceinline__ void poly_row(P psi, T fr, T* wt) {
 // Per-block maxima of |v| of every image of the launch (blockIdx.y), written to slot 7 of the
 // image's FP64 reduction scratch (the grid reductions use slots 0-4 and consume them within
 // their kernel); the spreading derives its fixed-point scales from them.  A NaN propagates.
+__device__ __forceinline__ double absmax_acc(double m, double x) {
+  const double a = fabs(x);
+  return (a > m || a != a) ? a : m;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_absmax(const ImgDev* __restrict__ imgs, VecArg in, int check) {
   const ImgDev& im = imgs[blockIdx.y];
   if (check && im.st->done) return;
   const T* v = vin<T>(im, in);
-  double m = 0.0;
-  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < im.N; i += (long long)kAbsBlocks * 256) {
-    const double a = fabs((double)v[i]);
-    m = (a > m || a != a) ? a : m;
+  constexpr int VW = 16 / (int)sizeof(T);              // elements per 16-byte load
+  typedef T TV __attribute__((ext_vector_type(VW)));
+  // 16-byte loads when the vector is 16-byte aligned (scalar loads otherwise)
+  const bool vec = ((size_t)v & 15) == 0;
+  const long long nv = vec ? im.N / VW : 0;
+  const long long stride = (long long)kAbsBlocks * 256;
+  double m0 = 0.0, m1 = 0.0;
+  long long i = blockIdx.x * 256LL + threadIdx.x;
+  for (; i + stride < nv; i += 2 * stride) {           // two loads in flight per thread
+    const TV a = reinterpret_cast<const TV*>(v)[i], b = reinterpret_cast<const TV*>(v)[i + stride];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) {
+      m0 = absmax_acc(m0, (double)a[k]);
+      m1 = absmax_acc(m1, (double)b[k]);
+    }
   }
+  if (i < nv) {
+    const TV a = reinterpret_cast<const TV*>(v)[i];
+#pragma unroll
+    for (int k = 0; k < VW; ++k) m0 = absmax_acc(m0, (double)a[k]);
+  }
+  for (long long j = nv * VW + blockIdx.x * 256LL + threadIdx.x; j < im.N; j += stride)
+    m1 = absmax_acc(m1, (double)v[j]);
   __shared__ double sh[256];
-  sh[threadIdx.x] = m;
+  sh[threadIdx.x] = absmax_acc(m0, m1);
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) {
-      const double o = sh[threadIdx.x + k];
-      if (o > sh[threadIdx.x] || o != o) sh[threadIdx.x] = o;
-    }
+    if ((int)threadIdx.x < k) sh[threadIdx.x] = absmax_acc(sh[threadIdx.x], sh[threadIdx.x + k]);
     __syncthreads();
   }
   if (threadIdx.x == 0) im.red[(size_t)blockIdx.x * 8 + 7] = sh[0];
@@ -249,8 +269,10 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   // fixed-point scale of this chunk from a bound of sum |v| over its nodes: max |v| of the
   // image (per-block maxima left by k_absmax in slot 7 of the image's reduction scratch) times
   // the chunk's node count
-  double vmax = lane < kAbsBlocks ? im.red[lane * 8 + 7] : 0.0;
-  for (int off = 32; off > 0; off >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
+  double vmax = 0.0;
+#pragma unroll
+  for (int k = 0; k < kAbsBlocks / 64; ++k) vmax = absmax_acc(vmax, im.red[(lane + 64 * k) * 8 + 7]);
+  for (int off = 32; off > 0; off >>= 1) vmax = absmax_acc(vmax, __shfl_xor(vmax, off));
   __syncthreads();
   const double tot = vmax * (double)(job.pend - job.pbeg);
   auto out = padded + (long long)job.slot * slot_stride;
