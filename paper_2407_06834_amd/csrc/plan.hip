@@ -123,15 +123,18 @@ __global__ void k_coords(const T* __restrict__ F, long long N, int L,
         bi = (int)fl;
         fr = (T)(u - fl);
         if (fr >= (T)1) { fr = (T)0; bi += 1; }
-        bi = ((bi % p.n[dd]) + p.n[dd]) % p.n[dd];
+        bi &= p.n[dd] - 1;                       // periodic wrap (n is a power of two)
       }
       b[dd] = bi;
       e.f[dd] = fr;
     }
     e.base = (unsigned)b[0] | ((unsigned)b[1] << 8) | ((unsigned)b[2] << 16);
     ent[idx] = e;
-    const int g = ((b[0] / p.ts[0]) * p.nts[1] + b[1] / p.ts[1]) * p.nts[2] + b[2] / p.ts[2];
-    const int lc = ((b[0] % p.ts[0]) * p.ts[1] + b[1] % p.ts[1]) * p.ts[2] + b[2] % p.ts[2];
+    // tile and cell within the tile (tile extents are powers of two)
+    const int l0 = __builtin_ctz(p.ts[0]), l1 = __builtin_ctz(p.ts[1]), l2 = __builtin_ctz(p.ts[2]);
+    const int g = ((b[0] >> l0) * p.nts[1] + (b[1] >> l1)) * p.nts[2] + (b[2] >> l2);
+    const int lc = ((b[0] & (p.ts[0] - 1)) * p.ts[1] + (b[1] & (p.ts[1] - 1))) * p.ts[2] +
+                   (b[2] & (p.ts[2] - 1));
     key[idx] = ((p.tile_off + (unsigned)g) << p.cell_bits) | (unsigned)lc;
   }
 }
