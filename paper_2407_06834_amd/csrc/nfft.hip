@@ -28,8 +28,6 @@ constexpr int kSpreadWaves = 4;
 constexpr int kSpreadThreads = 64 * kSpreadWaves;
 constexpr int kConvThreads = 256;
 constexpr int kGatherThreads = 256;
-constexpr int kAbsBlocks = 512;      // blocks per image of k_absmax
-static_assert(kAbsBlocks % 64 == 0 && kAbsBlocks <= kRedBlocks, "absmax partials: whole lanes, inside the scratch");
 
 __device__ __forceinline__ int wrap(int c, int n) {
   c %= n;
@@ -178,52 +176,6 @@ __device__ __forceinline__ void poly_row(P psi, T fr, T* wt) {
 // TSC = 8: every 3-D window of the launch has 8^3 tiles, so the padded extents and strides are
 // compile-time constants (LDS offsets fold into the instructions); TSC = 0 reads them from the
 // window descriptor.
-// Per-block maxima of |v| of every image of the launch (blockIdx.y), written to slot 7 of the
-// image's FP64 reduction scratch (the grid reductions use slots 0-4 and consume them within
-// their kernel); the spreading derives its fixed-point scales from them.  A NaN propagates.
-__device__ __forceinline__ double absmax_acc(double m, double x) {
-  const double a = fabs(x);
-  return (a > m || a != a) ? a : m;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) k_absmax(const ImgDev* __restrict__ imgs, VecArg in, int check) {
-  const ImgDev& im = imgs[blockIdx.y];
-  if (check && im.st->done) return;
-  const T* v = vin<T>(im, in);
-  constexpr int VW = 16 / (int)sizeof(T);              // elements per 16-byte load
-  typedef T TV __attribute__((ext_vector_type(VW)));
-  // 16-byte loads when the vector is 16-byte aligned (scalar loads otherwise)
-  const bool vec = ((size_t)v & 15) == 0;
-  const long long nv = vec ? im.N / VW : 0;
-  const long long stride = (long long)kAbsBlocks * 256;
-  double m0 = 0.0, m1 = 0.0;
-  long long i = blockIdx.x * 256LL + threadIdx.x;
-  for (; i + stride < nv; i += 2 * stride) {           // two loads in flight per thread
-    const TV a = reinterpret_cast<const TV*>(v)[i], b = reinterpret_cast<const TV*>(v)[i + stride];
-#pragma unroll
-    for (int k = 0; k < VW; ++k) {
-      m0 = absmax_acc(m0, (double)a[k]);
-      m1 = absmax_acc(m1, (double)b[k]);
-    }
-  }
-  if (i < nv) {
-    const TV a = reinterpret_cast<const TV*>(v)[i];
-#pragma unroll
-    for (int k = 0; k < VW; ++k) m0 = absmax_acc(m0, (double)a[k]);
-  }
-  for (long long j = nv * VW + blockIdx.x * 256LL + threadIdx.x; j < im.N; j += stride)
-    m1 = absmax_acc(m1, (double)v[j]);
-  __shared__ double sh[256];
-  sh[threadIdx.x] = absmax_acc(m0, m1);
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) sh[threadIdx.x] = absmax_acc(sh[threadIdx.x], sh[threadIdx.x + k]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) im.red[(size_t)blockIdx.x * 8 + 7] = sh[0];
-}
-
 template <typename T, int W, int TD, int TSC>
 __global__ void __launch_bounds__(kSpreadThreads)
 k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int job0,
@@ -256,6 +208,7 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
   extern __shared__ unsigned char smem_raw[];
   Acc* acc = reinterpret_cast<Acc*>(smem_raw);
   Acc* acc_lo = acc + (kTwo ? w.pe[0] * w.pe[1] * w.pe[2] : 0);
+  __shared__ double s_part[kSpreadWaves];
   constexpr int PEC = (TD == 3 && TSC > 0) ? TSC + W - 1 : 0;
   const int pe1 = PEC ? PEC : w.pe[1], pe2 = PEC ? PEC : w.pe[2];
   const int cells = PEC ? PEC * PEC * PEC : w.pe[0] * pe1 * pe2;
@@ -266,15 +219,37 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
     acc[c] = (Acc)0;
     if constexpr (kTwo) acc_lo[c] = (Acc)0;
   }
-  // fixed-point scale of this chunk from a bound of sum |v| over its nodes: max |v| of the
-  // image (per-block maxima left by k_absmax in slot 7 of the image's reduction scratch) times
-  // the chunk's node count
-  double vmax = 0.0;
+  // fixed-point scale of this chunk: 2^e <= sum |v| over its nodes.  The row-broadcast path
+  // (kDpp below) loads the values of all of a wavefront's rounds here, all loads in flight, and
+  // keeps them in registers for its node loop; the generic path sums them in a separate pass.
+  const int npts = job.pend - job.pbeg;
+  const int per = (npts + kSpreadWaves - 1) / kSpreadWaves;
+  const int q0 = job.pbeg + wave * per, q1 = min(job.pend, q0 + per);
+  constexpr bool kDppV = TD == 3 && (W == 6 || W == 8) && sizeof(T) == 4;
+  constexpr int kRounds = kMaxChunk / (64 * kSpreadWaves);
+  static_assert(kMaxChunk % (64 * kSpreadWaves) == 0, "whole rounds per wavefront");
+  float vreg[kDppV ? kRounds : 1];
+  double sa = 0.0;
+  if constexpr (kDppV) {
+    int ireg[kRounds];
 #pragma unroll
-  for (int k = 0; k < kAbsBlocks / 64; ++k) vmax = absmax_acc(vmax, im.red[(lane + 64 * k) * 8 + 7]);
-  for (int off = 32; off > 0; off >>= 1) vmax = absmax_acc(vmax, __shfl_xor(vmax, off));
+    for (int r = 0; r < kRounds; ++r) {
+      const int p = q0 + 64 * r + lane;
+      ireg[r] = p < q1 ? g_idx[p] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) vreg[r] = (q0 + 64 * r + lane < q1) ? (float)v[ireg[r]] : 0.0f;
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) sa += fabs((double)vreg[r]);
+  } else {
+    for (int p = job.pbeg + threadIdx.x; p < job.pend; p += kSpreadThreads)
+      sa += fabs((double)v[g_idx[p]]);
+  }
+  for (int off = 32; off > 0; off >>= 1) sa += __shfl_xor(sa, off);
+  if (lane == 0) s_part[wave] = sa;
   __syncthreads();
-  const double tot = vmax * (double)(job.pend - job.pbeg);
+  double tot = 0.0;
+  for (int k = 0; k < kSpreadWaves; ++k) tot += s_part[k];
   auto out = padded + (long long)job.slot * slot_stride;
   if (!(tot > 0.0)) {
     for (int c = threadIdx.x; c < cells; c += kSpreadThreads) out[c] = (T)0;
@@ -361,20 +336,16 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
       }
     }
   };
-  const int npts = job.pend - job.pbeg;
-  const int per = (npts + kSpreadWaves - 1) / kSpreadWaves;
-  const int q0 = job.pbeg + wave * per, q1 = min(job.pend, q0 + per);
   if constexpr (kDpp) {
     // the wavefront's own 64 entries of s_stage; LDS operations of one wavefront execute in
     // order, so the stores are visible to the loads of the node loop below and the next
     // round's stores follow them
     float4* stg = s_stage + wave * 64;
     float (&aw)[W] = accr[0];
-    // the next round's entries are loaded while this round's nodes are spread (the input
-    // value through the node index after the node loop, once the index has arrived)
+    // the next round's entries are loaded while this round's nodes are spread; the input
+    // values are in vreg (round r of the wavefront in vreg[0] at round r)
     unsigned n_mb = 0u;
-    float n_f0 = 0.0f, n_f1 = 0.0f, n_f2 = 0.0f, n_v = 0.0f;
-    int n_idx = 0;
+    float n_f0 = 0.0f, n_f1 = 0.0f, n_f2 = 0.0f;
     auto load_round = [&](int bp) {
       const int pp = bp + lane;
       if (pp < q1) {
@@ -382,13 +353,9 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
         n_f0 = g_frac[pp];
         n_f1 = g_frac[LN + pp];
         n_f2 = g_frac[2 * LN + pp];
-        n_idx = g_idx[pp];
       }
     };
-    if (q0 < q1) {
-      load_round(q0);
-      if (q0 + lane < q1) n_v = v[n_idx];
-    }
+    if (q0 < q1) load_round(q0);
     for (int base_p = q0; base_p < q1; base_p += 64) {
       const int p = base_p + lane;
       const bool ok = p < q1;
@@ -397,7 +364,9 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
       nd.x = ok ? fmaf(n_f0, 2.0f, -1.0f) : 0.0f;
       nd.y = ok ? fmaf(n_f1, 2.0f, -1.0f) : 0.0f;
       nd.z = ok ? fmaf(n_f2, 2.0f, -1.0f) : 0.0f;
-      nd.w = ok ? n_v * scale_t : 0.0f;
+      nd.w = ok ? vreg[0] * scale_t : 0.0f;
+#pragma unroll
+      for (int r = 0; r + 1 < kRounds; ++r) vreg[r] = vreg[r + 1];
       const bool more = base_p + 64 < q1;
       if (more) load_round(base_p + 64);
       __builtin_amdgcn_wave_barrier();
@@ -431,7 +400,6 @@ k_spread(const WinDev* __restrict__ wins, const TileJob* __restrict__ jobs, int 
         node(q, __uint_as_float(sw[0]));
         if (q + 1 < cnt) node(q + 1, __uint_as_float(sw[1]));
       }
-      if (more && base_p + 64 + lane < q1) n_v = v[n_idx];
       __builtin_amdgcn_wave_barrier();
     }
   } else
@@ -1448,11 +1416,6 @@ void launch_tiles(const LaunchSet& ls, VecArg in, int check, hipStream_t s, bool
   // spreading accumulates in fixed point: two 32-bit words (FP32) or one 64-bit word (FP64) per
   // cell; gathering stages the tile in T
   const size_t lds = (size_t)ls.max_padded * (gather ? sizeof(T) : 8);
-  if (!gather) {
-    hipLaunchKernelGGL(k_absmax<T>, dim3(kAbsBlocks, ls.n_imgs), dim3(256), 0, s, ls.d_imgs, in,
-                       check);
-    NLD_HIP(hipGetLastError());
-  }
   for (int g = 0; g < 3; ++g) {
     const int j0 = ls.tjob_begin[g], nj = ls.tjob_begin[g + 1] - j0;
     if (nj == 0) continue;

@@ -13,6 +13,7 @@ namespace nld {
 
 constexpr int kMaxTap = 16;        // 2m for m <= 8
 constexpr int kRedBlocks = 512;    // blocks of the FP64 reductions
+constexpr int kMaxChunk = 4096;    // most nodes of one spreading / gathering workgroup
 constexpr int kRedThreads = 256;
 
 // ------------------------------------------------------------------ errors

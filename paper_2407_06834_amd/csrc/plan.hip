@@ -19,10 +19,10 @@ namespace nld {
 
 namespace {
 
-constexpr int kTileChunk = 4096;     // nodes per spreading / gathering workgroup (default)
+constexpr int kTileChunk = kMaxChunk;   // nodes per spreading / gathering workgroup (default)
 int tile_chunk() {
   const char* e = std::getenv("NLD_TILE_CHUNK");
-  return e ? std::max(64, std::min(1 << 20, std::atoi(e))) : kTileChunk;
+  return e ? std::max(64, std::min(kMaxChunk, std::atoi(e))) : kTileChunk;
 }
 constexpr int kMaxCellBits = 16;     // sort key = global tile << cell_bits | cell within the tile
 
