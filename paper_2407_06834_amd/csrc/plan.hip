@@ -95,7 +95,7 @@ __device__ inline int floordiv(int a, int b) { return (a >= 0) ? a / b : -((-a +
 
 // Grid coordinates of every (window, node): packed base cell and fractional offsets in one
 // entry (16 bytes in FP32, 32 in FP64, so that the permutation into sorted order reads one
-// cache line per entry), and the global key of the tile that holds the base cell.
+// cache line per entry), and the sort key within the window: tile << cell_bits | cell.
 template <typename T> struct CoordEntry;
 template <> struct __attribute__((aligned(16))) CoordEntry<float> { unsigned base; float f[3]; };
 template <> struct __attribute__((aligned(16))) CoordEntry<double> { unsigned base, pad; double f[3]; };
@@ -135,18 +135,26 @@ __global__ void k_coords(const T* __restrict__ F, long long N, int L,
     const int g = ((b[0] >> l0) * p.nts[1] + (b[1] >> l1)) * p.nts[2] + (b[2] >> l2);
     const int lc = ((b[0] & (p.ts[0] - 1)) * p.ts[1] + (b[1] & (p.ts[1] - 1))) * p.ts[2] +
                    (b[2] & (p.ts[2] - 1));
-    key[idx] = ((p.tile_off + (unsigned)g) << p.cell_bits) | (unsigned)lc;
+    key[idx] = ((unsigned)g << p.cell_bits) | (unsigned)lc;   // key within the window
   }
 }
 
-// First position of every tile in the sorted key array (lower bound of tile << cell_bits),
-// for tiles 0..ntiles.
-__global__ void k_key_offsets(const unsigned* __restrict__ keys, long long n, int ntiles,
-                              int cell_bits, unsigned* __restrict__ off) {
+// First position of every global tile (0..ntiles) in the sorted entries: window l's entries
+// occupy [l N, (l + 1) N), sorted by their key within the window (tile << cell_bits | cell), so
+// tile k of window l starts at the lower bound of (k - tile_off) << cell_bits in that segment.
+__global__ void k_key_offsets(const unsigned* __restrict__ keys, long long N, int L,
+                              const CoordParams* __restrict__ cp, int ntiles, int cell_bits,
+                              unsigned* __restrict__ off) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k > ntiles) return;
-  const unsigned long long target = (unsigned long long)k << cell_bits;
-  long long lo = 0, hi = n;
+  if (k == ntiles) {
+    off[k] = (unsigned)(N * L);
+    return;
+  }
+  int l = 0;
+  while (l + 1 < L && (int)cp[l + 1].tile_off <= k) ++l;
+  const unsigned long long target = (unsigned long long)(k - (int)cp[l].tile_off) << cell_bits;
+  long long lo = (long long)l * N, hi = (long long)(l + 1) * N;
   while (lo < hi) {
     const long long mid = (lo + hi) >> 1;
     if ((unsigned long long)keys[mid] < target) lo = mid + 1;
@@ -308,54 +316,63 @@ void exclusive_scan(unsigned* data, long long n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- stable LSD radix sort
-// 8-bit digits, blocks of 4 wavefronts and 4096 items.  A wavefront ranks its 1024 items in
+// Segments of equal length (one per window) sorted separately, 7-bit digits, blocks of 4
+// wavefronts and 4096 items that never straddle a segment.  A wavefront ranks its 1024 items in
 // order with ballots (equal keys keep their input order), the block places its items in digit
-// order in LDS, and then writes every digit's run to its global position with consecutive
-// threads on consecutive positions (runs of 16 items on average where the digits are random,
-// instead of single items).
+// order in LDS and writes every digit's run to its global position with consecutive threads on
+// consecutive positions.  The block offsets come from one exclusive scan over (segment, digit,
+// block), so every segment stays in place.
 constexpr int kSortThreads = 256, kSortPer = 16, kSortItems = kSortThreads * kSortPer;
 constexpr int kSortWaveItems = kSortItems / (kSortThreads / 64);
+constexpr int kSortBits = 7, kSortBuckets = 1 << kSortBits;
 
 __global__ void __launch_bounds__(kSortThreads)
-k_radix_hist(const unsigned* __restrict__ keys, long long n, int shift, unsigned* __restrict__ hist,
-             int nblk) {
-  __shared__ unsigned h[256];
-  h[threadIdx.x] = 0;
+k_radix_hist(const unsigned* __restrict__ keys, long long seglen, int bps, int shift,
+             unsigned* __restrict__ hist) {
+  __shared__ unsigned h[kSortBuckets];
+  if (threadIdx.x < kSortBuckets) h[threadIdx.x] = 0;
   __syncthreads();
-  const long long b0 = (long long)blockIdx.x * kSortItems;
+  const int seg = blockIdx.x / bps, lb = blockIdx.x - seg * bps;
+  const long long b0 = (long long)seg * seglen + (long long)lb * kSortItems;
+  const long long e = (long long)seg * seglen + min(seglen, (long long)(lb + 1) * kSortItems);
   for (int r = 0; r < kSortPer; ++r) {
     const long long i = b0 + r * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    if (i < e) atomicAdd(&h[(keys[i] >> shift) & (kSortBuckets - 1)], 1u);
   }
   __syncthreads();
-  hist[(long long)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x < kSortBuckets)
+    hist[((long long)seg * kSortBuckets + threadIdx.x) * bps + lb] = h[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const unsigned* __restrict__ kin, const unsigned* __restrict__ vin,
-                unsigned* __restrict__ kout, unsigned* __restrict__ vout, long long n, int shift,
-                const unsigned* __restrict__ offs, int nblk) {
+                unsigned* __restrict__ kout, unsigned* __restrict__ vout, long long seglen,
+                int bps, int shift, const unsigned* __restrict__ offs) {
   constexpr int kWaves = kSortThreads / 64;
-  __shared__ unsigned wcnt[kWaves][256];    // per-wavefront counts, then their prefixes
-  __shared__ unsigned lstart[256];          // first block-local position of every digit
-  __shared__ unsigned goff[256];            // first global position of every digit (this block)
+  static_assert(kSortBuckets % 64 == 0 && kSortBuckets <= kSortThreads, "whole wavefronts of digits");
+  __shared__ unsigned wcnt[kWaves][kSortBuckets];   // per-wavefront counts, then their prefixes
+  __shared__ unsigned lstart[kSortBuckets];         // first block-local position of every digit
+  __shared__ unsigned goff[kSortBuckets];           // first global position of every digit
   __shared__ unsigned wsum[kWaves];
   __shared__ unsigned skey[kSortItems], sval[kSortItems];
   const int t = threadIdx.x, lane = t & 63;
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-  for (int d = t; d < kWaves * 256; d += kSortThreads) (&wcnt[0][0])[d] = 0u;
-  goff[t] = offs[(long long)t * nblk + blockIdx.x];
+  const int seg = blockIdx.x / bps, lb = blockIdx.x - seg * bps;
+  const long long s0 = (long long)seg * seglen;
+  const long long e = s0 + min(seglen, (long long)(lb + 1) * kSortItems);
+  for (int d = t; d < kWaves * kSortBuckets; d += kSortThreads) (&wcnt[0][0])[d] = 0u;
+  if (t < kSortBuckets) goff[t] = offs[((long long)seg * kSortBuckets + t) * bps + lb];
   __syncthreads();
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const long long b0 = (long long)blockIdx.x * kSortItems + (long long)wv * kSortWaveItems;
+  const long long b0 = s0 + (long long)lb * kSortItems + (long long)wv * kSortWaveItems;
   unsigned key[kSortPer], val[kSortPer], pos[kSortPer];   // pos: digit << 16 | rank in wavefront
   for (int r = 0; r < kSortPer; ++r) {
     const long long i = b0 + r * 64 + lane;
-    const bool valid = i < n;
+    const bool valid = i < e;
     const unsigned k = valid ? kin[i] : 0u;
-    const unsigned dg = (k >> shift) & 255u;
+    const unsigned dg = (k >> shift) & (kSortBuckets - 1);
     unsigned long long mask = __ballot(valid);
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < kSortBits; ++bit) {
       const bool set = (dg >> bit) & 1u;
       const unsigned long long bal = __ballot(set);
       mask &= set ? bal : ~bal;
@@ -374,22 +391,27 @@ k_radix_scatter(const unsigned* __restrict__ kin, const unsigned* __restrict__ v
   }
   __syncthreads();
   // digit t: prefixes over the wavefronts and the block-local start (exclusive scan of totals)
-  unsigned c[kWaves], tot = 0;
-  for (int w = 0; w < kWaves; ++w) {
-    c[w] = tot;
-    tot += wcnt[w][t];
+  // (the digits are whole wavefronts, so the branches below are uniform per wavefront)
+  unsigned c[kWaves], tot = 0, inc = 0;
+  if (t < kSortBuckets) {
+    for (int w = 0; w < kWaves; ++w) {
+      c[w] = tot;
+      tot += wcnt[w][t];
+    }
+    inc = tot;
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned y = __shfl_up(inc, off);
+      if (lane >= off) inc += y;
+    }
+    if (lane == 63) wsum[wv] = inc;
   }
-  unsigned inc = tot;
-  for (int off = 1; off < 64; off <<= 1) {
-    const unsigned y = __shfl_up(inc, off);
-    if (lane >= off) inc += y;
-  }
-  if (lane == 63) wsum[wv] = inc;
   __syncthreads();
-  unsigned before = 0;
-  for (int w = 0; w < wv; ++w) before += wsum[w];
-  lstart[t] = before + inc - tot;
-  for (int w = 0; w < kWaves; ++w) wcnt[w][t] = c[w];
+  if (t < kSortBuckets) {
+    unsigned before = 0;
+    for (int w = 0; w < wv; ++w) before += wsum[w];
+    lstart[t] = before + inc - tot;
+    for (int w = 0; w < kWaves; ++w) wcnt[w][t] = c[w];
+  }
   __syncthreads();
   for (int r = 0; r < kSortPer; ++r) {
     if (pos[r] == 0xffffffffu) continue;
@@ -399,44 +421,47 @@ k_radix_scatter(const unsigned* __restrict__ kin, const unsigned* __restrict__ v
     sval[q] = val[r];
   }
   __syncthreads();
-  const long long nv = n - (long long)blockIdx.x * kSortItems;
-  const int nvalid = nv < kSortItems ? (int)nv : kSortItems;
+  const int nvalid = (int)(e - (s0 + (long long)lb * kSortItems));
   for (int r = 0; r < kSortPer; ++r) {
     const int q = r * kSortThreads + t;
     if (q >= nvalid) break;
     const unsigned k = skey[q];
-    const unsigned dg = (k >> shift) & 255u;
+    const unsigned dg = (k >> shift) & (kSortBuckets - 1);
     const unsigned dst = goff[dg] + (unsigned)q - lstart[dg];
     kout[dst] = k;
     vout[dst] = sval[q];
   }
 }
 
-// Sorts (keys, vals) by the low key_bits bits of keys, stably.  Result in keys / vals.
-void radix_sort_pairs(unsigned* keys, unsigned* vals, long long n, int key_bits, hipStream_t s) {
-  if (n <= 1) return;
-  const int nblk = (int)((n + kSortItems - 1) / kSortItems);
-  unsigned* k2 = dalloc<unsigned>(n, s);
-  unsigned* v2 = dalloc<unsigned>(n, s);
-  unsigned* hist = dalloc<unsigned>(256LL * nblk, s);
+// Sorts each of nseg consecutive segments of seglen (key, value) pairs by the low key_bits bits
+// of the keys, stably.  keys / vals are replaced by the buffers that hold the result (the other
+// pair is returned to the buffer cache).
+void radix_sort_segments(unsigned*& keys, unsigned*& vals, int nseg, long long seglen,
+                         int key_bits, hipStream_t s) {
+  if ((long long)nseg * seglen <= 1) return;
+  const int bps = (int)((seglen + kSortItems - 1) / kSortItems);
+  const int nblk = nseg * bps;
+  unsigned* k2 = dalloc<unsigned>((long long)nseg * seglen, s);
+  unsigned* v2 = dalloc<unsigned>((long long)nseg * seglen, s);
+  unsigned* hist = dalloc<unsigned>((long long)kSortBuckets * nblk, s);
   unsigned *ka = keys, *va = vals, *kb = k2, *vb = v2;
-  const int passes = std::max(1, (key_bits + 7) / 8);
+  const int passes = std::max(1, (key_bits + kSortBits - 1) / kSortBits);
   for (int pss = 0; pss < passes; ++pss) {
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, s, ka, n, 8 * pss, hist, nblk);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kSortThreads), 0, s, ka, seglen, bps,
+                       kSortBits * pss, hist);
     NLD_HIP(hipGetLastError());
-    exclusive_scan(hist, 256LL * nblk, s);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortThreads), 0, s, ka, va, kb, vb, n,
-                       8 * pss, hist, nblk);
+    exclusive_scan(hist, (long long)kSortBuckets * nblk, s);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kSortThreads), 0, s, ka, va, kb, vb,
+                       seglen, bps, kSortBits * pss, hist);
     NLD_HIP(hipGetLastError());
     std::swap(ka, kb);
     std::swap(va, vb);
   }
-  if (ka != keys) {
-    NLD_HIP(hipMemcpyAsync(keys, ka, n * sizeof(unsigned), hipMemcpyDeviceToDevice, s));
-    NLD_HIP(hipMemcpyAsync(vals, va, n * sizeof(unsigned), hipMemcpyDeviceToDevice, s));
-  }
-  dfree(k2, s);
-  dfree(v2, s);
+  // ka / va hold the result; kb / vb the other pair
+  keys = ka;
+  vals = va;
+  dfree(kb, s);
+  dfree(vb, s);
   dfree(hist, s);
 }
 
@@ -889,15 +914,19 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   unsigned* val = dalloc<unsigned>(LN, s);
   hipLaunchKernelGGL(k_iota, dim3(grid_for(LN)), dim3(256), 0, s, val, LN);
   NLD_HIP(hipGetLastError());
+  // bits of the key within a window: its tile count and the cell bits
   int kbits = 1;
-  while ((1u << kbits) < tile_total) ++kbits;
+  for (int l = 0; l < L; ++l) {
+    const unsigned nt = (unsigned)(P.wins[l].nts[0] * P.wins[l].nts[1] * P.wins[l].nts[2]);
+    while ((1u << kbits) < nt) ++kbits;
+  }
   if (kbits + cell_bits > 32) throw std::invalid_argument("too many tiles");
-  radix_sort_pairs(key, val, LN, kbits + cell_bits, s);
+  radix_sort_segments(key, val, L, N, kbits + cell_bits, s);
   // tile offsets first: the host builds the schedules from them while the device permutes the
   // node entries into sorted order
   unsigned* toff = dalloc<unsigned>(tile_total + 1, s);
-  hipLaunchKernelGGL(k_key_offsets, dim3((tile_total + 256) / 256), dim3(256), 0, s, key, LN,
-                     (int)tile_total, cell_bits, toff);
+  hipLaunchKernelGGL(k_key_offsets, dim3((tile_total + 256) / 256), dim3(256), 0, s, key, N, L,
+                     (const CoordParams*)d_cp, (int)tile_total, cell_bits, toff);
   NLD_HIP(hipGetLastError());
   unsigned* ht_pin = (unsigned*)pinned_get((tile_total + 1) * sizeof(unsigned), false);
   NLD_HIP(hipMemcpyAsync(ht_pin, toff, (tile_total + 1) * sizeof(unsigned), hipMemcpyDeviceToHost, s));
