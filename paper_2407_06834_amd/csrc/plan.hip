@@ -29,26 +29,28 @@ constexpr int kMaxCellBits = 16;     // sort key = global tile << cell_bits | ce
 template <typename T>
 __global__ void k_features(const T* __restrict__ img, int n1, int n2, int rho, int with_pos,
                            T* __restrict__ F) {
+  // One pixel per lane, all its features: x covers a row's columns, y strides over the rows;
+  // each feature row's stores are contiguous across the wavefront.
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= n2) return;
   const long long N = (long long)n1 * n2;
   const int P = 2 * rho + 1;
-  const int d = (with_pos ? 2 : 0) + P * P;
-  const long long total = N * d;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int k = (int)(idx / N);
-    const long long i = idx - (long long)k * N;
-    const int row = (int)(i / n2), col = (int)(i - (long long)row * n2);
-    T val;
-    if (with_pos && k == 0) {
-      val = (T)((double)col / (double)n2);
-    } else if (with_pos && k == 1) {
-      val = (T)((double)row / (double)n1);
-    } else {
-      const int p = k - (with_pos ? 2 : 0);
-      const int r = row + p / P - rho, c = col + p % P - rho;
-      val = (r >= 0 && r < n1 && c >= 0 && c < n2) ? img[(long long)r * n2 + c] : (T)0;
+  for (int row = blockIdx.y; row < n1; row += gridDim.y) {
+    T* out = F + (long long)row * n2 + col;
+    if (with_pos) {
+      out[0] = (T)((double)col / (double)n2);
+      out[N] = (T)((double)row / (double)n1);
+      out += 2 * N;
     }
-    F[idx] = val;
+    for (int a = 0; a < P; ++a) {
+      const int r = row + a - rho;
+      const bool rin = r >= 0 && r < n1;
+      for (int b = 0; b < P; ++b) {
+        const int c = col + b - rho;
+        *out = (rin && c >= 0 && c < n2) ? img[(long long)r * n2 + c] : (T)0;
+        out += N;
+      }
+    }
   }
 }
 
@@ -58,16 +60,28 @@ __global__ void k_minmax(const T* __restrict__ F, long long N, const int* __rest
                          double* __restrict__ part) {
   const int c = blockIdx.y;
   const T* x = F + (long long)cols[c] * N;
-  double lo = INFINITY, hi = -INFINITY;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
-    const double v = (double)x[i];
-    lo = fmin(lo, v);
-    hi = fmax(hi, v);
+  // Min and max are taken in T (exact; the conversion to double is monotonic), eight
+  // independent loads in flight per lane.
+  T lo = (T)INFINITY, hi = (T)-INFINITY;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  for (; i + 7 * stride < N; i += 8 * stride) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = x[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      lo = fmin(lo, v[u]);
+      hi = fmax(hi, v[u]);
+    }
+  }
+  for (; i < N; i += stride) {
+    lo = fmin(lo, x[i]);
+    hi = fmax(hi, x[i]);
   }
   __shared__ double slo[256], shi[256];
-  slo[threadIdx.x] = lo;
-  shi[threadIdx.x] = hi;
+  slo[threadIdx.x] = (double)lo;
+  shi[threadIdx.x] = (double)hi;
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
@@ -100,16 +114,17 @@ template <typename T> struct CoordEntry;
 template <> struct __attribute__((aligned(16))) CoordEntry<float> { unsigned base; float f[3]; };
 template <> struct __attribute__((aligned(16))) CoordEntry<double> { unsigned base, pad; double f[3]; };
 
+// Grid: y is the window (its parameters are wave-uniform), x strides over the nodes.  Also
+// writes the identity permutation that the sort carries along (val = flat entry index).
 template <typename T>
-__global__ void k_coords(const T* __restrict__ F, long long N, int L,
+__global__ void k_coords(const T* __restrict__ F, long long N,
                          const CoordParams* __restrict__ cp, CoordEntry<T>* __restrict__ ent,
-                         unsigned* __restrict__ key) {
-  const long long total = N * L;
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int l = (int)(idx / N);
-    const long long j = idx - (long long)l * N;
-    const CoordParams p = cp[l];
+                         unsigned* __restrict__ key, unsigned* __restrict__ val) {
+  const int l = blockIdx.y;
+  const CoordParams p = cp[l];
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < N;
+       j += (long long)gridDim.x * blockDim.x) {
+    const long long idx = (long long)l * N + j;
     int b[3];
     CoordEntry<T> e{};
     for (int dd = 0; dd < 3; ++dd) {
@@ -136,6 +151,7 @@ __global__ void k_coords(const T* __restrict__ F, long long N, int L,
     const int lc = ((b[0] & (p.ts[0] - 1)) * p.ts[1] + (b[1] & (p.ts[1] - 1))) * p.ts[2] +
                    (b[2] & (p.ts[2] - 1));
     key[idx] = ((unsigned)g << p.cell_bits) | (unsigned)lc;   // key within the window
+    val[idx] = (unsigned)idx;
   }
 }
 
@@ -465,27 +481,24 @@ void radix_sort_segments(unsigned*& keys, unsigned*& vals, int nseg, long long s
   dfree(hist, s);
 }
 
-// Copy the coordinates of sorted entries: out[e] = in[(window of e, node of e)].
+// Copy the coordinates of sorted entries: out[e] = in[(window of e, node of e)].  Every
+// window's entries are sorted within their own segment [l N, (l + 1) N), so the window of a
+// sorted entry is its segment: grid y is the window, x strides over the segment.
 template <typename T>
-__global__ void k_gather_entries(const unsigned* __restrict__ vals, long long n, long long N,
+__global__ void k_gather_entries(const unsigned* __restrict__ vals, long long N,
                                  const CoordEntry<T>* __restrict__ ent, int* __restrict__ out_idx,
                                  unsigned* __restrict__ out_base, T* __restrict__ out_frac,
                                  long long out_stride) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+  const long long seg = (long long)blockIdx.y * N;
+  for (long long e = seg + blockIdx.x * (long long)blockDim.x + threadIdx.x; e < seg + N;
        e += (long long)gridDim.x * blockDim.x) {
     const unsigned flat = vals[e];
-    const long long l = flat / N, j = flat - l * N;
+    const long long j = (long long)flat - seg;
     const CoordEntry<T> c = ent[flat];
     out_idx[e] = (int)j;
     out_base[e] = c.base;
     for (int dd = 0; dd < 3; ++dd) out_frac[dd * out_stride + e] = c.f[dd];
   }
-}
-
-__global__ void k_iota(unsigned* __restrict__ x, long long n) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x)
-    x[i] = (unsigned)i;
 }
 
 template <typename T>
@@ -587,13 +600,13 @@ void* plan_buffer(size_t bytes, hipStream_t s) { return dev_get(std::max<size_t>
 
 void launch_features(const void* img, int n1, int n2, int rho, int with_pos, nld_prec prec,
                      void* F, hipStream_t s) {
-  const long long total = (long long)n1 * n2 * ((with_pos ? 2 : 0) + (2 * rho + 1) * (2 * rho + 1));
+  const dim3 grid((unsigned)((n2 + 255) / 256), (unsigned)std::min(n1, 1024));
   if (prec == NLD_FP32)
-    hipLaunchKernelGGL(k_features<float>, dim3(grid_for(total)), dim3(256), 0, s,
-                       (const float*)img, n1, n2, rho, with_pos, (float*)F);
+    hipLaunchKernelGGL(k_features<float>, grid, dim3(256), 0, s, (const float*)img, n1, n2, rho,
+                       with_pos, (float*)F);
   else
-    hipLaunchKernelGGL(k_features<double>, dim3(grid_for(total)), dim3(256), 0, s,
-                       (const double*)img, n1, n2, rho, with_pos, (double*)F);
+    hipLaunchKernelGGL(k_features<double>, grid, dim3(256), 0, s, (const double*)img, n1, n2,
+                       rho, with_pos, (double*)F);
   NLD_HIP(hipGetLastError());
 }
 
@@ -906,14 +919,13 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   upload(P, d_cp, cp.data(), L * sizeof(CoordParams), s);
   CoordEntry<T>* ent = dalloc<CoordEntry<T>>(LN, s);
   unsigned* key = dalloc<unsigned>(LN, s);
-  hipLaunchKernelGGL(k_coords<T>, dim3(grid_for(LN)), dim3(256), 0, s, (const T*)features, N, L, d_cp,
-                     ent, key);
+  unsigned* val = dalloc<unsigned>(LN, s);
+  const dim3 win_grid(std::min<unsigned>(grid_for(N), (unsigned)((65536 + L - 1) / L)), (unsigned)L);
+  hipLaunchKernelGGL(k_coords<T>, win_grid, dim3(256), 0, s, (const T*)features, N, d_cp, ent, key,
+                     val);
   NLD_HIP(hipGetLastError());
 
   // ---- 4. nodes of every window sorted (stably) by tile; tile offsets by binary search
-  unsigned* val = dalloc<unsigned>(LN, s);
-  hipLaunchKernelGGL(k_iota, dim3(grid_for(LN)), dim3(256), 0, s, val, LN);
-  NLD_HIP(hipGetLastError());
   // bits of the key within a window: its tile count and the cell bits
   int kbits = 1;
   for (int l = 0; l < L; ++l) {
@@ -936,7 +948,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   P.g_idx = dalloc<int>(LN, s);
   P.g_base = dalloc<unsigned>(LN, s);
   P.g_frac = dalloc<T>(3 * LN, s);
-  hipLaunchKernelGGL(k_gather_entries<T>, dim3(grid_for(LN)), dim3(256), 0, s, val, LN, N,
+  hipLaunchKernelGGL(k_gather_entries<T>, win_grid, dim3(256), 0, s, val, N,
                      (const CoordEntry<T>*)ent, P.g_idx, P.g_base, (T*)P.g_frac, LN);
   NLD_HIP(hipGetLastError());
   const hipError_t ev_err = hipEventSynchronize(ev_off);
