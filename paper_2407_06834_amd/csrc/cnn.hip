@@ -50,15 +50,17 @@ __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float
 
 enum Epi { EPI_RELU = 0, EPI_OUT = 1, EPI_MASK = 2 };
 
-// Input channels (f, cond[0..nc-1], zeros) of every pixel.
+// Input channels (f, cond[0..nc-1], zeros) of every pixel; grid y is the image.
 __global__ void k_cnn_input(const float* __restrict__ f, const float* __restrict__ cond, int nc,
-                            long long hw, long long total, unsigned short* __restrict__ x) {
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < total;
-       p += (long long)gridDim.x * blockDim.x) {
-    const long long img = p / hw;
-    unsigned short v[C];
+                            long long hw, unsigned short* __restrict__ x) {
+  const long long img = blockIdx.y;
+  // every channel but f's is the same for all pixels of the image
+  unsigned short v[C];
+  for (int c = 1; c < C; ++c) v[c] = (c - 1 < nc) ? f2bf(cond[img * nc + c - 1]) : (unsigned short)0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < hw;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long p = img * hw + i;
     v[0] = f2bf(f[p]);
-    for (int c = 1; c < C; ++c) v[c] = (c - 1 < nc) ? f2bf(cond[img * nc + c - 1]) : (unsigned short)0;
     u32x4* dst = reinterpret_cast<u32x4*>(x + p * C);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -121,31 +123,42 @@ k_conv(const unsigned short* __restrict__ x, const unsigned short* __restrict__ 
       const bf16x8 a = *reinterpret_cast<const bf16x8*>(xs + (r * (TW + 2) + c) * HP + 8 * kq);
 #pragma unroll
       for (int hh = 0; hh < NH; ++hh)
-        acc[q][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t][hh], acc[q][hh], 0, 0, 0);
+        acc[q][hh] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[t][hh], a, acc[q][hh], 0, 0, 0);
     }
   }
-  // lane holds D[pixel 4 kq + j][cout 16 hh + lr] of each fragment
+  // the weights are the left operand, so lane holds D^T[cout 16 hh + 4 kq + j][pixel lr] of
+  // each fragment: four consecutive output channels of one pixel, stored as 8 bytes
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int gy = y0 + 2 * wave + (q >> 1);
-    if (gy >= h) continue;
+    const int gx = x0 + 16 * (q & 1) + lr;
+    if (gy >= h || gx >= w) continue;
+    const long long p = ibase + (long long)gy * w + gx;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gx = x0 + 16 * (q & 1) + 4 * kq + j;
-      if (gx >= w) continue;
-      const long long p = ibase + (long long)gy * w + gx;
-#pragma unroll
-      for (int hh = 0; hh < NH; ++hh) {
-        const int co = 16 * hh + lr;
-        const float v = acc[q][hh][j];
+    for (int hh = 0; hh < NH; ++hh) {
+      const int co = 16 * hh + 4 * kq;
+      const f32x4 v = acc[q][hh];
+      if constexpr (EPI == EPI_OUT) {
+        if (co == 0) yout[p] = f[p] + v[0] + bias[0];
+      } else {
+        unsigned short o[4];
         if constexpr (EPI == EPI_RELU) {
-          const float z = v + bias[co];
-          y[p * C + co] = f2bf(z > 0.f ? z : 0.f);
-        } else if constexpr (EPI == EPI_MASK) {
-          y[p * C + co] = bf2f(mask[p * C + co]) > 0.f ? f2bf(v) : (unsigned short)0;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float z = v[j] + bias[co + j];
+            o[j] = f2bf(z > 0.f ? z : 0.f);
+          }
         } else {
-          if (co == 0) yout[p] = f[p] + v + bias[0];
+          const uint2 mk = *reinterpret_cast<const uint2*>(mask + p * C + co);
+          const unsigned short mv[4] = {(unsigned short)(mk.x & 0xffffu), (unsigned short)(mk.x >> 16),
+                                        (unsigned short)(mk.y & 0xffffu), (unsigned short)(mk.y >> 16)};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) o[j] = bf2f(mv[j]) > 0.f ? f2bf(v[j]) : (unsigned short)0;
         }
+        uint2 st;
+        st.x = o[0] | ((unsigned)o[1] << 16);
+        st.y = o[2] | ((unsigned)o[3] << 16);
+        *reinterpret_cast<uint2*>(y + p * C + co) = st;
       }
     }
   }
@@ -434,9 +447,9 @@ void forward(Cnn& net, const float* f, const float* cond_host, int n, int h, int
   const int nc = net.cin - 1;
   if (nc > 0)
     NLD_HIP(hipMemcpyAsync(net.cond, cond_host, (size_t)n * nc * sizeof(float), hipMemcpyHostToDevice, s));
-  const unsigned nb = (unsigned)std::min<long long>(65536, (px + 255) / 256);
-  hipLaunchKernelGGL(k_cnn_input, dim3(nb), dim3(256), 0, s, f, net.cond, nc, (long long)h * w, px,
-                     net.act[0]);
+  const long long hw = (long long)h * w;
+  const unsigned nb = (unsigned)std::max<long long>(1, std::min<long long>(65536 / n, (hw + 255) / 256));
+  hipLaunchKernelGGL(k_cnn_input, dim3(nb, n), dim3(256), 0, s, f, net.cond, nc, hw, net.act[0]);
   for (int k = 0; k < kLayers - 1; ++k)
     hipLaunchKernelGGL((k_conv<32, EPI_RELU>), g, dim3(256), 0, s, net.act[k],
                        net.wf + (size_t)k * 9 * C * C, net.bias + k * C, h, w, net.act[k + 1],

@@ -885,34 +885,6 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     while ((1LL << cell_bits) < cells) ++cell_bits;
   }
   for (int l = 0; l < L; ++l) cp[l].cell_bits = cell_bits;
-  std::vector<T> coef_all, coef_dv_all;   // host staging, alive until the final synchronisation
-  upload_tables<T>(P, coef_all, coef_dv_all, s);
-
-  // window polynomials (same cutoff for every window; the shape b depends on M / n)
-  std::vector<T> psi_all;   // host staging buffers live until the final synchronisation
-  {
-    const int deg = PsiDeg<T>::value;
-    const int W = 2 * P.wins[0].m;
-    psi_all.assign((size_t)L * W * (deg + 1), (T)0);
-    P.psi_err = 0.0;
-    std::vector<double> c;                    // fitted once per distinct window shape (m, b)
-    int c_m = -1;
-    double c_b = 0.0;
-    for (int l = 0; l < L; ++l) {
-      double err = 0.0;
-      if (P.wins[l].m != c_m || P.wins[l].b != c_b) {
-        c = fit_window(P.wins[l].m, P.wins[l].b, deg, &err);
-        c_m = P.wins[l].m;
-        c_b = P.wins[l].b;
-        P.psi_err = std::max(P.psi_err, err);
-      }
-      for (size_t q = 0; q < c.size(); ++q) psi_all[(size_t)l * W * (deg + 1) + q] = (T)c[q];
-    }
-    P.psi = dalloc<T>((long long)psi_all.size(), s);
-    upload(P, P.psi, psi_all.data(), psi_all.size() * sizeof(T), s);
-    for (int l = 0; l < L; ++l) P.wins[l].psi = (const T*)P.psi + (size_t)l * W * (deg + 1);
-  }
-
   // ---- 3. coordinates of every (window, node)
   const long long LN = N * L;
   CoordParams* d_cp = dalloc<CoordParams>(L, s);
@@ -951,76 +923,36 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_entries<T>, win_grid, dim3(256), 0, s, val, N,
                      (const CoordEntry<T>*)ent, P.g_idx, P.g_base, (T*)P.g_frac, LN);
   NLD_HIP(hipGetLastError());
-  const hipError_t ev_err = hipEventSynchronize(ev_off);
-  (void)hipEventDestroy(ev_off);
-  NLD_HIP(ev_err);
-  std::vector<unsigned> ht(ht_pin, ht_pin + tile_total + 1);
-  pinned_put(ht_pin);
-  if (ht[tile_total] != (unsigned)LN) throw std::runtime_error("internal: tile offsets do not add up");
+  // Fourier multipliers and window polynomials: host work that only the products need, done
+  // while the device sorts and permutes
+  std::vector<T> coef_all, coef_dv_all;   // host staging, alive until the final synchronisation
+  upload_tables<T>(P, coef_all, coef_dv_all, s);
 
-  // ---- 5. schedules (host): chunks of the nodes of every non-empty tile, grouped by t;
-  // every chunk owns one padded-tile slot; the fold sums a tile's slots in order.
-  std::vector<TileJob> jobs;
-  std::vector<int> slot0(tile_total, 0), nslot(tile_total, 0);
-  int slots = 0;
-  const long long chunk = tile_chunk();
-  for (int g = 0; g < 3; ++g) {
-    P.tjob_begin[g] = (int)jobs.size();
-    for (int l = 0; l < L; ++l) {
-      const WinDev& w = P.wins[l];
-      if (w.t != g + 1) continue;      // windows without kept dimensions need no grid
-      const int nt = w.nts[0] * w.nts[1] * w.nts[2];
-      for (int tl = 0; tl < nt; ++tl) {
-        const unsigned gt = (unsigned)w.tile_off + tl;
-        const long long b0 = ht[gt], b1 = ht[gt + 1];
-        if (b1 == b0) continue;
-        slot0[gt] = slots;
-        for (long long c = b0; c < b1; c += chunk) {
-          jobs.push_back(TileJob{l, tl, (int)c, (int)std::min(b1, c + chunk), slots});
-          ++slots;
-          ++nslot[gt];
-        }
-      }
-    }
-  }
-  P.tjob_begin[3] = (int)jobs.size();
-  // the gathering: tile order (neighbouring tiles stage overlapping grid cells), largest chunks
-  // first within each XCD's range
-  P.h_gjobs = jobs;
+  // window polynomials (same cutoff for every window; the shape b depends on M / n)
+  std::vector<T> psi_all;   // host staging buffers live until the final synchronisation
   {
-    std::vector<TileJob> gj(jobs);
-    for (int g = 0; g < 3; ++g) gather_order(gj, P.tjob_begin[g], P.tjob_begin[g + 1]);
-    P.d_gjobs = dalloc<TileJob>(std::max<size_t>(1, gj.size()), s);
-    upload(P, P.d_gjobs, gj.data(), gj.size() * sizeof(TileJob), s);
-  }
-  // largest chunks first within each group, so the long workgroups start early
-  for (int g = 0; g < 3; ++g)
-    std::stable_sort(jobs.begin() + P.tjob_begin[g], jobs.begin() + P.tjob_begin[g + 1],
-                     [](const TileJob& a, const TileJob& b) {
-                       return (a.pend - a.pbeg) > (b.pend - b.pbeg);
-                     });
-  if (std::getenv("NLD_PLAN_STATS")) {
-    long long ne = 0, maxc = 0;
-    for (unsigned gt = 0; gt < tile_total; ++gt) {
-      const long long c = (long long)ht[gt + 1] - ht[gt];
-      ne += (c > 0);
-      maxc = std::max(maxc, c);
+    const int deg = PsiDeg<T>::value;
+    const int W = 2 * P.wins[0].m;
+    psi_all.assign((size_t)L * W * (deg + 1), (T)0);
+    P.psi_err = 0.0;
+    std::vector<double> c;                    // fitted once per distinct window shape (m, b)
+    int c_m = -1;
+    double c_b = 0.0;
+    for (int l = 0; l < L; ++l) {
+      double err = 0.0;
+      if (P.wins[l].m != c_m || P.wins[l].b != c_b) {
+        c = fit_window(P.wins[l].m, P.wins[l].b, deg, &err);
+        c_m = P.wins[l].m;
+        c_b = P.wins[l].b;
+        P.psi_err = std::max(P.psi_err, err);
+      }
+      for (size_t q = 0; q < c.size(); ++q) psi_all[(size_t)l * W * (deg + 1) + q] = (T)c[q];
     }
-    std::fprintf(stderr, "plan: N=%lld L=%d tiles=%u nonempty=%lld jobs=%zu slots=%d max_tile_nodes=%lld "
-                 "max_padded=%lld psi_err=%.2e\n", (long long)N, L, tile_total, ne, jobs.size(), slots,
-                 maxc, max_padded, P.psi_err);
+    P.psi = dalloc<T>((long long)psi_all.size(), s);
+    upload(P, P.psi, psi_all.data(), psi_all.size() * sizeof(T), s);
+    for (int l = 0; l < L; ++l) P.wins[l].psi = (const T*)P.psi + (size_t)l * W * (deg + 1);
   }
-  P.h_tjobs = jobs;
-  P.d_tjobs = dalloc<TileJob>(std::max<size_t>(1, jobs.size()), s);
-  upload(P, P.d_tjobs, jobs.data(), jobs.size() * sizeof(TileJob), s);
-  P.n_tiles_total = (int)tile_total;
-  P.tile_slot0 = dalloc<int>(tile_total, s);
-  P.tile_nslot = dalloc<int>(tile_total, s);
-  upload(P, P.tile_slot0, slot0.data(), tile_total * sizeof(int), s);
-  upload(P, P.tile_nslot, nslot.data(), tile_total * sizeof(int), s);
-  P.max_padded = (int)max_padded;
-  P.slot_stride = max_padded;
-  P.padded = dalloc<T>((long long)std::max(1, slots) * max_padded, s);
+  // ---- 5. fold, plane and convolution jobs (they depend on the windows only)
   // fold jobs: per tile for 3-D windows (uniform tile size), 256 grid cells each otherwise
   std::vector<FoldJob> fj;
   std::vector<Fold3Job> f3;
@@ -1120,6 +1052,76 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
       upload(P, P.d_conv_u[ax], cjobs_all[ax].data(), cjobs_all[ax].size() * sizeof(ConvJob), s);
     }
   }
+  const hipError_t ev_err = hipEventSynchronize(ev_off);
+  (void)hipEventDestroy(ev_off);
+  NLD_HIP(ev_err);
+  std::vector<unsigned> ht(ht_pin, ht_pin + tile_total + 1);
+  pinned_put(ht_pin);
+  if (ht[tile_total] != (unsigned)LN) throw std::runtime_error("internal: tile offsets do not add up");
+
+  // ---- 6. schedules (host): chunks of the nodes of every non-empty tile, grouped by t;
+  // every chunk owns one padded-tile slot; the fold sums a tile's slots in order.
+  std::vector<TileJob> jobs;
+  std::vector<int> slot0(tile_total, 0), nslot(tile_total, 0);
+  int slots = 0;
+  const long long chunk = tile_chunk();
+  for (int g = 0; g < 3; ++g) {
+    P.tjob_begin[g] = (int)jobs.size();
+    for (int l = 0; l < L; ++l) {
+      const WinDev& w = P.wins[l];
+      if (w.t != g + 1) continue;      // windows without kept dimensions need no grid
+      const int nt = w.nts[0] * w.nts[1] * w.nts[2];
+      for (int tl = 0; tl < nt; ++tl) {
+        const unsigned gt = (unsigned)w.tile_off + tl;
+        const long long b0 = ht[gt], b1 = ht[gt + 1];
+        if (b1 == b0) continue;
+        slot0[gt] = slots;
+        for (long long c = b0; c < b1; c += chunk) {
+          jobs.push_back(TileJob{l, tl, (int)c, (int)std::min(b1, c + chunk), slots});
+          ++slots;
+          ++nslot[gt];
+        }
+      }
+    }
+  }
+  P.tjob_begin[3] = (int)jobs.size();
+  // the gathering: tile order (neighbouring tiles stage overlapping grid cells), largest chunks
+  // first within each XCD's range
+  P.h_gjobs = jobs;
+  {
+    std::vector<TileJob> gj(jobs);
+    for (int g = 0; g < 3; ++g) gather_order(gj, P.tjob_begin[g], P.tjob_begin[g + 1]);
+    P.d_gjobs = dalloc<TileJob>(std::max<size_t>(1, gj.size()), s);
+    upload(P, P.d_gjobs, gj.data(), gj.size() * sizeof(TileJob), s);
+  }
+  // largest chunks first within each group, so the long workgroups start early
+  for (int g = 0; g < 3; ++g)
+    std::stable_sort(jobs.begin() + P.tjob_begin[g], jobs.begin() + P.tjob_begin[g + 1],
+                     [](const TileJob& a, const TileJob& b) {
+                       return (a.pend - a.pbeg) > (b.pend - b.pbeg);
+                     });
+  if (std::getenv("NLD_PLAN_STATS")) {
+    long long ne = 0, maxc = 0;
+    for (unsigned gt = 0; gt < tile_total; ++gt) {
+      const long long c = (long long)ht[gt + 1] - ht[gt];
+      ne += (c > 0);
+      maxc = std::max(maxc, c);
+    }
+    std::fprintf(stderr, "plan: N=%lld L=%d tiles=%u nonempty=%lld jobs=%zu slots=%d max_tile_nodes=%lld "
+                 "max_padded=%lld psi_err=%.2e\n", (long long)N, L, tile_total, ne, jobs.size(), slots,
+                 maxc, max_padded, P.psi_err);
+  }
+  P.h_tjobs = jobs;
+  P.d_tjobs = dalloc<TileJob>(std::max<size_t>(1, jobs.size()), s);
+  upload(P, P.d_tjobs, jobs.data(), jobs.size() * sizeof(TileJob), s);
+  P.n_tiles_total = (int)tile_total;
+  P.tile_slot0 = dalloc<int>(tile_total, s);
+  P.tile_nslot = dalloc<int>(tile_total, s);
+  upload(P, P.tile_slot0, slot0.data(), tile_total * sizeof(int), s);
+  upload(P, P.tile_nslot, nslot.data(), tile_total * sizeof(int), s);
+  P.max_padded = (int)max_padded;
+  P.slot_stride = max_padded;
+  P.padded = dalloc<T>((long long)std::max(1, slots) * max_padded, s);
 
   // ---- 7. work buffers
   P.grid_total = grid_total;
