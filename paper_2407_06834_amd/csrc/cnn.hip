@@ -5,11 +5,12 @@
 //
 // Layout: activations NHWC with 32 BF16 channels per pixel (64 bytes; unused channels are
 // zero), so a pixel's channels are one contiguous vector.  A convolution is an implicit GEMM
-// per 8 x 32 pixel tile: for each of the 9 taps, D[pixels][cout] += X_shift[pixels][cin] *
-// W_tap[cin][cout] with v_mfma_f32_16x16x32_bf16 (16 pixels x 16 output channels x 32 input
-// channels per instruction).  The input tile with its one-pixel halo is staged in LDS (80-byte
-// pixel stride against bank conflicts); every wave keeps the 18 weight fragments of the layer in
-// registers.  The backward pass to the input is the same kernel with the transposed, flipped
+// per 8 x 32 pixel tile: for each of the 9 taps, D^T[cout][pixels] += W_tap^T[cout][cin] *
+// X_shift^T[cin][pixels] with v_mfma_f32_16x16x32_bf16 (16 output channels x 16 pixels x 32
+// input channels per instruction; with the weights as the left operand a lane's accumulators
+// are four consecutive channels of one pixel, one 8-byte store).  The input tile with its
+// one-pixel halo is staged in LDS (80-byte pixel stride against bank conflicts); every wave
+// keeps the 18 weight fragments of the layer in registers.  The backward pass to the input is the same kernel with the transposed, flipped
 // weights and a ReLU-mask epilogue; the weight gradient contracts over pixels with both
 // operands staged channel-major in LDS (three copies of the input tile shifted by -1, 0, +1
 // columns keep every fragment read 16-byte aligned) and writes per-block partials that a
@@ -76,26 +77,54 @@ __global__ void k_cnn_input(const float* __restrict__ f, const float* __restrict
 
 // 3x3 convolution of one 8 x 32 tile of one image.  wt: [9][32 cout][32 cin] BF16.  COUT 32, or
 // 16 with only channel 0 meaningful (last layer).  Epilogues: ReLU(acc + b) -> BF16; f + acc +
-// b (channel 0) -> FP32 out; acc * (mask > 0) -> BF16.
-template <int COUT, int EPI>
+// b (channel 0) -> FP32 out; acc * (mask > 0) -> BF16.  FROM_IMG: the input channels are built
+// while staging, from the image f and the nc conditioning values of each image (the channels
+// k_cnn_input stores), so inference of the first layer reads 4 bytes per pixel instead of 64.
+template <int COUT, int EPI, bool FROM_IMG = false>
 __global__ void __launch_bounds__(256)
 k_conv(const unsigned short* __restrict__ x, const unsigned short* __restrict__ wt,
        const float* __restrict__ bias, int h, int w, unsigned short* __restrict__ y,
        float* __restrict__ yout, const float* __restrict__ f,
-       const unsigned short* __restrict__ mask) {
+       const unsigned short* __restrict__ mask, const float* __restrict__ cond = nullptr,
+       int nc = 0) {
   constexpr int NH = COUT / 16;
   __shared__ __attribute__((aligned(16))) unsigned short xs[(TH + 2) * (TW + 2) * HP];
   const int img = blockIdx.z;
   const int y0 = blockIdx.y * TH, x0 = blockIdx.x * TW;
   const long long ibase = (long long)img * h * w;
+  // FROM_IMG: the image's four 16-byte channel chunks with f = 0 (channel 0 is set per pixel)
+  __shared__ u32x4 cpat[4];
+  if constexpr (FROM_IMG) {
+    if (threadIdx.x < 4) {
+      unsigned short ch[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = 8 * (int)threadIdx.x + i;
+        ch[i] = (k >= 1 && k - 1 < nc) ? f2bf(cond[(long long)img * nc + k - 1]) : (unsigned short)0;
+      }
+      u32x4 v;
+      v.x = ch[0] | ((unsigned)ch[1] << 16);
+      v.y = ch[2] | ((unsigned)ch[3] << 16);
+      v.z = ch[4] | ((unsigned)ch[5] << 16);
+      v.w = ch[6] | ((unsigned)ch[7] << 16);
+      cpat[threadIdx.x] = v;
+    }
+    __syncthreads();
+  }
   // stage the halo tile: 10 x 34 pixels, 4 chunks of 16 bytes each
   for (int idx = threadIdx.x; idx < (TH + 2) * (TW + 2) * 4; idx += 256) {
     const int pl = idx >> 2, part = idx & 3;
     const int r = pl / (TW + 2), c = pl - r * (TW + 2);
     const int gy = y0 - 1 + r, gx = x0 - 1 + c;
     u32x4 v = {0u, 0u, 0u, 0u};
-    if (gy >= 0 && gy < h && gx >= 0 && gx < w)
-      v = *reinterpret_cast<const u32x4*>(x + (ibase + (long long)gy * w + gx) * C + part * 8);
+    if (gy >= 0 && gy < h && gx >= 0 && gx < w) {
+      if constexpr (FROM_IMG) {
+        v = cpat[part];
+        if (part == 0) v.x = (v.x & 0xffff0000u) | f2bf(f[ibase + (long long)gy * w + gx]);
+      } else {
+        v = *reinterpret_cast<const u32x4*>(x + (ibase + (long long)gy * w + gx) * C + part * 8);
+      }
+    }
     *reinterpret_cast<u32x4*>(xs + pl * HP + part * 8) = v;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -439,7 +468,8 @@ void pack(Cnn& net, hipStream_t s) {
 
 dim3 tiles_of(int n, int h, int w) { return dim3((w + TW - 1) / TW, (h + TH - 1) / TH, n); }
 
-void forward(Cnn& net, const float* f, const float* cond_host, int n, int h, int w, hipStream_t s) {
+void forward(Cnn& net, const float* f, const float* cond_host, int n, int h, int w, hipStream_t s,
+             bool keep_input) {
   const long long px = (long long)n * h * w;
   const dim3 g = tiles_of(n, h, w);
   ensure(net, px, n, (long long)g.x * g.y * g.z);
@@ -449,8 +479,13 @@ void forward(Cnn& net, const float* f, const float* cond_host, int n, int h, int
     NLD_HIP(hipMemcpyAsync(net.cond, cond_host, (size_t)n * nc * sizeof(float), hipMemcpyHostToDevice, s));
   const long long hw = (long long)h * w;
   const unsigned nb = (unsigned)std::max<long long>(1, std::min<long long>(65536 / n, (hw + 255) / 256));
-  hipLaunchKernelGGL(k_cnn_input, dim3(nb, n), dim3(256), 0, s, f, net.cond, nc, hw, net.act[0]);
-  for (int k = 0; k < kLayers - 1; ++k)
+  // the weight gradient of the first layer needs its stored input; inference builds it on the fly
+  if (keep_input)
+    hipLaunchKernelGGL(k_cnn_input, dim3(nb, n), dim3(256), 0, s, f, net.cond, nc, hw, net.act[0]);
+  else
+    hipLaunchKernelGGL((k_conv<32, EPI_RELU, true>), g, dim3(256), 0, s, nullptr, net.wf,
+                       net.bias, h, w, net.act[1], nullptr, f, nullptr, (const float*)net.cond, nc);
+  for (int k = keep_input ? 0 : 1; k < kLayers - 1; ++k)
     hipLaunchKernelGGL((k_conv<32, EPI_RELU>), g, dim3(256), 0, s, net.act[k],
                        net.wf + (size_t)k * 9 * C * C, net.bias + k * C, h, w, net.act[k + 1],
                        nullptr, nullptr, nullptr);
@@ -613,7 +648,7 @@ nld_status cnn_predict(nld_cnn_t h, const float* f, const float* cond, int32_t n
   if (!h || !f || !u0 || (!cond && h->net.cin > 1)) return cnn_fail(NLD_E_INVAL, "cnn_predict: null pointer");
   if (!shape_ok(n, hh, w)) return cnn_fail(NLD_E_INVAL, "cnn_predict: bad shape");
   return cnn_guard("cnn_predict", [&] {
-    nld::forward(h->net, f, cond, n, hh, w, s);
+    nld::forward(h->net, f, cond, n, hh, w, s, false);
     NLD_HIP(hipMemcpyAsync(u0, h->net.u0, (size_t)n * hh * w * sizeof(float), hipMemcpyDeviceToDevice, s));
     NLD_HIP(hipStreamSynchronize(s));
   });
@@ -625,7 +660,7 @@ nld_status cnn_loss_grad(nld_cnn_t h, const float* f, const float* cond, const f
     return cnn_fail(NLD_E_INVAL, "cnn_loss_grad: null pointer");
   if (!shape_ok(n, hh, w)) return cnn_fail(NLD_E_INVAL, "cnn_loss_grad: bad shape");
   return cnn_guard("cnn_loss_grad", [&] {
-    nld::forward(h->net, f, cond, n, hh, w, s);
+    nld::forward(h->net, f, cond, n, hh, w, s, true);
     nld::cnn_backward(h->net, target, n, hh, w, loss, s);
   });
 }

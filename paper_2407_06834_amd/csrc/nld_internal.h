@@ -238,6 +238,12 @@ struct Plan {
   CgState* st = nullptr;           // device CG state
   CgState* st_host = nullptr;      // pinned mirror
   std::vector<void*> staging;      // pinned blocks of host-to-device copies in flight
+  // while set, host tables collect in pending_blob (16-byte aligned) and reach the device in one
+  // copy and one scatter kernel (each separate copy costs about 10 us of stream time)
+  bool defer_uploads = false;
+  std::vector<unsigned char> pending_blob;
+  std::vector<void*> pending_dst;
+  std::vector<size_t> pending_off, pending_bytes;
   // launch description of this plan alone, its image table and a pinned host mirror of it; the
   // fused schedule (plane kernels) and the unfused one (three convolution passes), which the
   // per-window products of the gradient use
@@ -270,6 +276,8 @@ void release_plan(Plan& P);
 // the gathering's order of the tile-ordered jobs [begin, end): eight contiguous ranges, one per
 // XCD, each with its largest chunks first
 void gather_order(std::vector<TileJob>& jobs, size_t begin, size_t end);
+// stable sort of the jobs [b, e) by node count, largest first
+void sort_by_size_desc(std::vector<TileJob>& jobs, size_t b, size_t e);
 // device buffer of at least `bytes` from the library's per-device cache; a plan that stores it
 // in one of its buffer fields returns it to the cache on release
 void* plan_buffer(size_t bytes, hipStream_t s);

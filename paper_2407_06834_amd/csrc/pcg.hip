@@ -671,9 +671,7 @@ nld_status run_pcg_batched_t(Plan* const* plans, const double* alpha, const void
     std::vector<TileJob> tjobs, gjobs;
     for (int g = 0; g < 3; ++g) {
       // largest chunks first, across the whole batch; the gathering's order per XCD range
-      std::stable_sort(tj[g].begin(), tj[g].end(), [](const TileJob& a, const TileJob& b) {
-        return (a.pend - a.pbeg) > (b.pend - b.pbeg);
-      });
+      sort_by_size_desc(tj[g], 0, tj[g].size());
       ls.tjob_begin[g] = (int)tjobs.size();
       tjobs.insert(tjobs.end(), tj[g].begin(), tj[g].end());
       gjobs.insert(gjobs.end(), gj[g].begin(), gj[g].end());

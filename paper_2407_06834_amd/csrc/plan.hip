@@ -301,11 +301,44 @@ inline void dfree(void* p, hipStream_t s) {
   g_dev_pending[s].push_back(p);
 }
 
+// Segment i of a staged blob: bytes at blob + off go to dst.
+struct UploadSeg {
+  unsigned long long dst, off, bytes;
+};
+
+// Copies every segment of the blob to its buffer (grid x: segment, y: strided part of it);
+// 16-byte words where the destination, offset and length allow, bytes otherwise.
+__global__ void k_scatter_copy(const unsigned char* __restrict__ blob,
+                               const UploadSeg* __restrict__ segs) {
+  const UploadSeg g = segs[blockIdx.x];
+  unsigned char* dst = reinterpret_cast<unsigned char*>(g.dst);
+  const unsigned char* src = blob + g.off;
+  const unsigned long long step = (unsigned long long)gridDim.y * blockDim.x;
+  const unsigned long long t0 = (unsigned long long)blockIdx.y * blockDim.x + threadIdx.x;
+  if (((g.dst | g.off) & 15ull) == 0) {
+    const unsigned long long nw = g.bytes / 16;
+    for (unsigned long long i = t0; i < nw; i += step)
+      reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+    for (unsigned long long i = nw * 16 + t0; i < g.bytes; i += step) dst[i] = src[i];
+  } else {
+    for (unsigned long long i = t0; i < g.bytes; i += step) dst[i] = src[i];
+  }
+}
+
 // Host tables reach the device through pinned staging blocks: a copy from pageable memory holds
 // the host until it has finished, tens of microseconds each.  The blocks return to the pool at
 // the plan's next stream synchronisation (staging_done).
 static void upload(Plan& P, void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (bytes == 0) return;
+  if (P.defer_uploads) {
+    const size_t off = (P.pending_blob.size() + 15) & ~(size_t)15;
+    P.pending_blob.resize(off + bytes);
+    std::memcpy(P.pending_blob.data() + off, src, bytes);
+    P.pending_dst.push_back(dst);
+    P.pending_off.push_back(off);
+    P.pending_bytes.push_back(bytes);
+    return;
+  }
   void* p = pinned_get(bytes, false);
   P.staging.push_back(p);
   std::memcpy(p, src, bytes);
@@ -315,6 +348,33 @@ static void staging_done(Plan& P, hipStream_t s) {   // call only after synchron
   for (void* p : P.staging) pinned_put(p);
   P.staging.clear();
   dev_synced(s);
+}
+
+// The deferred tables: one host-to-device copy of the blob and its segment table, then one
+// kernel that copies every segment to its buffer.
+static void flush_uploads(Plan& P, hipStream_t s) {
+  P.defer_uploads = false;
+  const size_t nseg = P.pending_dst.size();
+  if (nseg > 0) {
+    std::vector<UploadSeg> seg(nseg);
+    for (size_t i = 0; i < nseg; ++i)
+      seg[i] = UploadSeg{(unsigned long long)(uintptr_t)P.pending_dst[i], P.pending_off[i],
+                         P.pending_bytes[i]};
+    const size_t toff = (P.pending_blob.size() + 15) & ~(size_t)15;
+    const size_t total = toff + nseg * sizeof(UploadSeg);
+    P.pending_blob.resize(total);
+    std::memcpy(P.pending_blob.data() + toff, seg.data(), nseg * sizeof(UploadSeg));
+    unsigned char* dblob = dalloc<unsigned char>((long long)total, s);
+    upload(P, dblob, P.pending_blob.data(), total, s);
+    hipLaunchKernelGGL(k_scatter_copy, dim3((unsigned)nseg, 16), dim3(256), 0, s,
+                       (const unsigned char*)dblob, (const UploadSeg*)(dblob + toff));
+    NLD_HIP(hipGetLastError());
+    dfree(dblob, s);
+  }
+  P.pending_blob.clear();
+  P.pending_dst.clear();
+  P.pending_off.clear();
+  P.pending_bytes.clear();
 }
 
 void exclusive_scan(unsigned* data, long long n, hipStream_t s) {
@@ -923,6 +983,8 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_entries<T>, win_grid, dim3(256), 0, s, val, N,
                      (const CoordEntry<T>*)ent, P.g_idx, P.g_base, (T*)P.g_frac, LN);
   NLD_HIP(hipGetLastError());
+  // the remaining host tables reach the device together at the end of the build
+  P.defer_uploads = true;
   // Fourier multipliers and window polynomials: host work that only the products need, done
   // while the device sorts and permutes
   std::vector<T> coef_all, coef_dv_all;   // host staging, alive until the final synchronisation
@@ -1095,11 +1157,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
     upload(P, P.d_gjobs, gj.data(), gj.size() * sizeof(TileJob), s);
   }
   // largest chunks first within each group, so the long workgroups start early
-  for (int g = 0; g < 3; ++g)
-    std::stable_sort(jobs.begin() + P.tjob_begin[g], jobs.begin() + P.tjob_begin[g + 1],
-                     [](const TileJob& a, const TileJob& b) {
-                       return (a.pend - a.pbeg) > (b.pend - b.pbeg);
-                     });
+  for (int g = 0; g < 3; ++g) sort_by_size_desc(jobs, P.tjob_begin[g], P.tjob_begin[g + 1]);
   if (std::getenv("NLD_PLAN_STATS")) {
     long long ne = 0, maxc = 0;
     for (unsigned gt = 0; gt < tile_total; ++gt) {
@@ -1187,7 +1245,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   im.st = P.st;
   im.red = P.red;
   P.d_img = dalloc<ImgDev>(1, s);
-  NLD_HIP(hipMemcpyAsync(P.d_img, P.img_host, sizeof(ImgDev), hipMemcpyHostToDevice, s));
+  upload(P, P.d_img, P.img_host, sizeof(ImgDev), s);
   LaunchSet& ls = P.ls;
   ls = LaunchSet{};
   ls.prec = P.prec;
@@ -1227,6 +1285,7 @@ static void build_plan_t(Plan& P, const void* features, hipStream_t s) {
   }
   lu.d_pjobs = nullptr;
   for (int g = 0; g < 3; ++g) lu.pjob_begin[g] = 0;
+  flush_uploads(P, s);
 
   dfree(d_cp, s);
   dfree(ent, s);
@@ -1295,14 +1354,30 @@ void pinned_put(void* p) {
   g_pinned_free[it->second].push_back(p);
 }
 
+// Stable sort of jobs [b, e) by node count, largest first: a counting sort over the chunk sizes
+// (at most kMaxChunk), the same order as a comparison-based stable sort in a fraction of the time.
+void sort_by_size_desc(std::vector<TileJob>& jobs, size_t b, size_t e) {
+  if (e - b < 2) return;
+  auto key = [](const TileJob& j) { return std::min(kMaxChunk + 1, std::max(0, j.pend - j.pbeg)); };
+  std::vector<unsigned> pos(kMaxChunk + 2, 0u);
+  for (size_t i = b; i < e; ++i) ++pos[key(jobs[i])];
+  unsigned acc = 0;
+  for (int sz = kMaxChunk + 1; sz >= 0; --sz) {
+    const unsigned c = pos[sz];
+    pos[sz] = acc;
+    acc += c;
+  }
+  std::vector<TileJob> tmp(e - b);
+  for (size_t i = b; i < e; ++i) tmp[pos[key(jobs[i])]++] = jobs[i];
+  std::copy(tmp.begin(), tmp.end(), jobs.begin() + b);
+}
+
 void gather_order(std::vector<TileJob>& jobs, size_t begin, size_t end) {
   const size_t nj = end - begin;
   for (size_t x = 0; x < 8; ++x) {
     const size_t b = begin + x * (nj / 8) + std::min(x, nj % 8);
     const size_t e = b + nj / 8 + (x < nj % 8 ? 1 : 0);
-    std::stable_sort(jobs.begin() + b, jobs.begin() + e, [](const TileJob& p, const TileJob& q) {
-      return (p.pend - p.pbeg) > (q.pend - q.pbeg);
-    });
+    sort_by_size_desc(jobs, b, e);
   }
 }
 
