@@ -20,7 +20,7 @@ both.  Inputs are uploaded before the timed region.
                     [--no-c2] [--profile-copy]
 
 `roofline` is the Laplacian product inside the timed solves (event-timed by the library on the
-solve's stream).  `roofline_c2` is the 512 x 512 FP32 product of the survey's HBM-bound case
+solve's stream).  `roofline_c2` is the 512 x 512 FP32 product, where the byte model is HBM-bound
 (9 windows, M = 64, n = 128, m = 4), timed the same way in a short section after the timed steps
 (--no-c2 skips it).  `traffic` fields are HBM bytes from rocprofv3 counters (FETCH_SIZE +
 WRITE_SIZE, copy-scaled), reported only while the kernel sources hash to the recorded value.
@@ -284,7 +284,7 @@ def main():
 
 
 def c2_product(nld, torch, sha):
-    """The 512 x 512 FP32 product of the survey's HBM-bound case (image seed 1: 20 rectangles,
+    """The 512 x 512 FP32 product, where the byte model is HBM-bound (image seed 1: 20 rectangles,
     12 discs, noise 0.1; 9 windows, sigma 0.1, M = 64, n = 128, m = 4), event-timed by the
     library inside two deflated PCG solves (alpha = 1, tol 1e-6)."""
     from paper_2407_06834_amd.synth import make_image
