@@ -80,8 +80,10 @@ __global__ void k_cnn_input(const float* __restrict__ f, const float* __restrict
 // b (channel 0) -> FP32 out; acc * (mask > 0) -> BF16.  FROM_IMG: the input channels are built
 // while staging, from the image f and the nc conditioning values of each image (the channels
 // k_cnn_input stores), so inference of the first layer reads 4 bytes per pixel instead of 64.
+// Four waves per SIMD: the compiler then keeps the weight fragments and the accumulators in 123
+// VGPRs (no AGPRs, no scratch) instead of 139 registers at three waves; five would spill.
 template <int COUT, int EPI, bool FROM_IMG = false>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_conv(const unsigned short* __restrict__ x, const unsigned short* __restrict__ wt,
        const float* __restrict__ bias, int h, int w, unsigned short* __restrict__ y,
        float* __restrict__ yout, const float* __restrict__ f,
